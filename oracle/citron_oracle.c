@@ -1,0 +1,340 @@
+/*
+ * Reference k-clique counter -- TEST INFRASTRUCTURE ONLY.
+ *
+ * Plain, slow, single-threaded C.  Only the tests, the smoke check and the
+ * benchmark's CPU-baseline leg may load this library; the product library
+ * never calls it and shares no code, header or table with it.
+ *
+ * What it computes (Lonkar & Beamer, "Accelerating Clique Counting in Sparse
+ * Real-World Graphs via Communication-Reducing Optimizations"):
+ *
+ *   count_k(G) = number of k-vertex subsets of V that are pairwise adjacent
+ *   (Section II, definition of a clique).
+ *
+ * It reaches that number the way the paper's method does, written out
+ * directly with no blocking or fusion:
+ *
+ *   1. Degree ordering (Section IV, Algorithm 3): u -> v is kept iff
+ *      d(u) < d(v), or d(u) == d(v) and u < v, with d the undirected
+ *      degree.  Out-lists keep the ascending id order of the input rows.
+ *   2. Counting (Section III, Algorithm 2, with the subgraph build of
+ *      Section V-B, Algorithm 5): the k-cliques are the sum over vertices u
+ *      of the (k-1)-cliques of the subgraph induced on N->(u); a subgraph's
+ *      vertex set is the sorted intersection of the parent's vertex set with
+ *      an out-list; at the level with two vertices left only intersection
+ *      sizes are summed (Section V-B, "Other Optimizations", second
+ *      heuristic); a subgraph with fewer vertices than the clique it still
+ *      has to hold is skipped when pruning is on (first heuristic, taken
+ *      with the exact bound).
+ *
+ * Counts are uint64 and wrap; a flag records whether any addition carried,
+ * which with non-negative addends happens iff the true total is >= 2^64.
+ *
+ * Pinned, in the CPU test-suite, by: brute-force subset enumeration on small
+ * graphs, closed forms (complete, Turan, bipartite, wheel, disjoint-clique
+ * and empty graphs), the worked example of Fig. 1, trace(A^3)/6 computed by
+ * a sparse-matrix library, and invariance under vertex relabelling.
+ */
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define ORACLE_OK 0
+#define ORACLE_EINVAL 1
+#define ORACLE_ENOMEM 2
+
+/* ---------------------------------------------------------------- input */
+
+/* Checks that (row_ptr, col) is a symmetric simple graph with sorted rows.
+ * Symmetry is checked by binary search of u in the row of each neighbour. */
+static int row_has(const int32_t* row_ptr, const int32_t* col, int32_t u, int32_t x)
+{
+    int64_t lo = row_ptr[u], hi = row_ptr[u + 1];
+    while (lo < hi) {
+        int64_t mid = lo + (hi - lo) / 2;
+        if (col[mid] < x) lo = mid + 1;
+        else hi = mid;
+    }
+    return lo < row_ptr[u + 1] && col[lo] == x;
+}
+
+int oracle_check_csr(int32_t n, const int32_t* row_ptr, const int32_t* col)
+{
+    if (n < 0 || !row_ptr) return ORACLE_EINVAL;
+    if (row_ptr[0] != 0) return ORACLE_EINVAL;
+    for (int32_t u = 0; u < n; ++u) {
+        if (row_ptr[u + 1] < row_ptr[u]) return ORACLE_EINVAL;
+        for (int64_t e = row_ptr[u]; e < row_ptr[u + 1]; ++e) {
+            int32_t v = col[e];
+            if (v < 0 || v >= n || v == u) return ORACLE_EINVAL;
+            if (e > row_ptr[u] && col[e - 1] >= v) return ORACLE_EINVAL;
+            if (!row_has(row_ptr, col, v, u)) return ORACLE_EINVAL;
+        }
+    }
+    return ORACLE_OK;
+}
+
+/* ------------------------------------------------- ordering (Algorithm 3) */
+
+/* omega(u) < omega(v): lower degree first, ties by lower id. */
+static int before(const int32_t* row_ptr, int32_t u, int32_t v)
+{
+    int64_t du = row_ptr[u + 1] - row_ptr[u];
+    int64_t dv = row_ptr[v + 1] - row_ptr[v];
+    return du < dv || (du == dv && u < v);
+}
+
+/* dag_ptr: int32[n+1], dag_col: int32[m] with m = nnz / 2. */
+int oracle_orient(int32_t n, const int32_t* row_ptr, const int32_t* col,
+                  int32_t* dag_ptr, int32_t* dag_col)
+{
+    int32_t* cursor = (int32_t*)malloc(sizeof(int32_t) * (size_t)(n + 1));
+    if (!cursor) return ORACLE_ENOMEM;
+    /* first pass: out-degree of every vertex */
+    dag_ptr[0] = 0;
+    for (int32_t u = 0; u < n; ++u) {
+        int32_t outdeg = 0;
+        for (int64_t e = row_ptr[u]; e < row_ptr[u + 1]; ++e)
+            if (before(row_ptr, u, col[e])) ++outdeg;
+        dag_ptr[u + 1] = outdeg;
+    }
+    /* prefix sum */
+    for (int32_t u = 0; u < n; ++u) dag_ptr[u + 1] += dag_ptr[u];
+    /* second pass: place the kept neighbours, a private cursor per row */
+    memcpy(cursor, dag_ptr, sizeof(int32_t) * (size_t)(n + 1));
+    for (int32_t u = 0; u < n; ++u)
+        for (int64_t e = row_ptr[u]; e < row_ptr[u + 1]; ++e)
+            if (before(row_ptr, u, col[e])) dag_col[cursor[u]++] = col[e];
+    free(cursor);
+    return ORACLE_OK;
+}
+
+/* ----------------------------------------------- counting (Algorithm 2/5) */
+
+typedef struct {
+    const int32_t* dptr;     /* oriented graph */
+    const int32_t* dcol;
+    int prune;
+    int overflow;
+    uint64_t count;
+    uint64_t* visits;        /* visits[j] = j-cliques met, j = 1..k (NULL ok) */
+    int32_t** level_buf;     /* one candidate buffer per recursion level */
+} count_ctx;
+
+static void add_checked(count_ctx* c, uint64_t x)
+{
+    uint64_t r;
+    if (__builtin_add_overflow(c->count, x, &r)) c->overflow = 1;
+    c->count = r;
+}
+
+static void add_visits(count_ctx* c, int j, uint64_t x)
+{
+    if (c->visits) c->visits[j] += x;
+}
+
+/* Sorted-list intersection by a two-pointer merge; writes into out (may be
+ * NULL to count only). */
+static int64_t intersect(const int32_t* a, int64_t na, const int32_t* b, int64_t nb,
+                         int32_t* out)
+{
+    int64_t i = 0, j = 0, s = 0;
+    while (i < na && j < nb) {
+        if (a[i] < b[j]) ++i;
+        else if (a[i] > b[j]) ++j;
+        else {
+            if (out) out[s] = a[i];
+            ++s; ++i; ++j;
+        }
+    }
+    return s;
+}
+
+/* Number of r-cliques of the oriented subgraph induced on the sorted vertex
+ * set cand[0..s), where `have` vertices of the clique are already chosen
+ * (used only for the per-size visit counts). */
+static void cliques_in(count_ctx* c, const int32_t* cand, int64_t s, int r, int have)
+{
+    add_visits(c, have + 1, (uint64_t)s);
+    if (r == 1) { add_checked(c, (uint64_t)s); return; }
+    if (c->prune && s < r) return;
+    if (r == 2) {
+        /* penultimate level: degrees only, no adjacency is built */
+        for (int64_t i = 0; i < s; ++i) {
+            int32_t w = cand[i];
+            int64_t d = intersect(c->dcol + c->dptr[w], c->dptr[w + 1] - c->dptr[w],
+                                  cand, s, NULL);
+            add_checked(c, (uint64_t)d);
+            add_visits(c, have + 2, (uint64_t)d);
+        }
+        return;
+    }
+    int32_t* next = c->level_buf[r];
+    for (int64_t i = 0; i < s; ++i) {
+        int32_t w = cand[i];
+        int64_t sn = intersect(c->dcol + c->dptr[w], c->dptr[w + 1] - c->dptr[w],
+                               cand, s, next);
+        cliques_in(c, next, sn, r - 1, have + 1);
+    }
+}
+
+static int32_t max_outdeg_of(int32_t n, const int32_t* dptr)
+{
+    int32_t mx = 0;
+    for (int32_t u = 0; u < n; ++u)
+        if (dptr[u + 1] - dptr[u] > mx) mx = dptr[u + 1] - dptr[u];
+    return mx;
+}
+
+static int ctx_init(count_ctx* c, int32_t n, const int32_t* dptr, const int32_t* dcol,
+                    int k, int prune, uint64_t* visits)
+{
+    memset(c, 0, sizeof(*c));
+    c->dptr = dptr;
+    c->dcol = dcol;
+    c->prune = prune;
+    c->visits = visits;
+    if (visits) memset(visits, 0, sizeof(uint64_t) * (size_t)(k + 1));
+    c->level_buf = (int32_t**)calloc((size_t)k + 2, sizeof(int32_t*));
+    if (!c->level_buf) return ORACLE_ENOMEM;
+    int32_t mx = max_outdeg_of(n, dptr);
+    for (int r = 0; r <= k + 1; ++r) {
+        c->level_buf[r] = (int32_t*)malloc(sizeof(int32_t) * ((size_t)mx + 1));
+        if (!c->level_buf[r]) return ORACLE_ENOMEM;
+    }
+    return ORACLE_OK;
+}
+
+static void ctx_free(count_ctx* c, int k)
+{
+    if (!c->level_buf) return;
+    for (int r = 0; r <= k + 1; ++r) free(c->level_buf[r]);
+    free(c->level_buf);
+}
+
+/* Count k-cliques of the oriented graph (dptr, dcol) rooted at the vertices
+ * u = first, first+step, ... < last (all of V for 0, 1, n).  k >= 1.
+ * visits: NULL or uint64[k+1]. */
+int oracle_count_dag(int32_t n, const int32_t* dptr, const int32_t* dcol, int32_t k,
+                     int32_t first, int32_t last, int32_t step, int32_t prune,
+                     uint64_t* count, int32_t* overflow, uint64_t* visits)
+{
+    if (k < 1 || step < 1 || first < 0 || last > n) return ORACLE_EINVAL;
+    count_ctx c;
+    if (ctx_init(&c, n, dptr, dcol, k, prune, visits) != ORACLE_OK) {
+        ctx_free(&c, k);
+        return ORACLE_ENOMEM;
+    }
+    for (int32_t u = first; u < last; u += step) {
+        int64_t du = dptr[u + 1] - dptr[u];
+        add_visits(&c, 1, 1);
+        if (k == 1) { add_checked(&c, 1); continue; }
+        cliques_in(&c, dcol + dptr[u], du, k - 1, 1);
+    }
+    *count = c.count;
+    *overflow = c.overflow;
+    ctx_free(&c, k);
+    return ORACLE_OK;
+}
+
+/* Whole pipeline: orient, then count.  Visits as above. */
+int oracle_count(int32_t n, const int32_t* row_ptr, const int32_t* col, int32_t k,
+                 int32_t prune, uint64_t* count, int32_t* overflow, uint64_t* visits)
+{
+    if (k < 1) return ORACLE_EINVAL;
+    int64_t m = (int64_t)row_ptr[n] / 2;
+    int32_t* dptr = (int32_t*)malloc(sizeof(int32_t) * ((size_t)n + 1));
+    int32_t* dcol = (int32_t*)malloc(sizeof(int32_t) * ((size_t)m + 1));
+    if (!dptr || !dcol) { free(dptr); free(dcol); return ORACLE_ENOMEM; }
+    int st = oracle_orient(n, row_ptr, col, dptr, dcol);
+    if (st == ORACLE_OK)
+        st = oracle_count_dag(n, dptr, dcol, k, 0, n, 1, prune, count, overflow, visits);
+    free(dptr);
+    free(dcol);
+    return st;
+}
+
+/* Edge-rooted counts: for each listed arc u -> v (which must be an arc of
+ * the oriented graph), the number of k-cliques whose two omega-lowest
+ * vertices are u and v, i.e. the (k-2)-cliques of the subgraph induced on
+ * N->(u) cap N->(v).  k >= 2. */
+int oracle_count_arcs(int32_t n, const int32_t* dptr, const int32_t* dcol, int32_t k,
+                      const int32_t* arc_u, const int32_t* arc_v, int64_t narcs,
+                      uint64_t* out, int32_t* overflow)
+{
+    if (k < 2) return ORACLE_EINVAL;
+    count_ctx c;
+    if (ctx_init(&c, n, dptr, dcol, k, 1, NULL) != ORACLE_OK) {
+        ctx_free(&c, k);
+        return ORACLE_ENOMEM;
+    }
+    int32_t* cand = c.level_buf[k + 1];
+    int any_overflow = 0;
+    for (int64_t i = 0; i < narcs; ++i) {
+        int32_t u = arc_u[i], v = arc_v[i];
+        c.count = 0;
+        c.overflow = 0;
+        if (k == 2) { out[i] = 1; continue; }
+        int64_t s = intersect(dcol + dptr[u], dptr[u + 1] - dptr[u],
+                              dcol + dptr[v], dptr[v + 1] - dptr[v], cand);
+        cliques_in(&c, cand, s, k - 2, 2);
+        out[i] = c.count;
+        any_overflow |= c.overflow;
+    }
+    *overflow = any_overflow;
+    ctx_free(&c, k);
+    return ORACLE_OK;
+}
+
+/* Per-arc work statistics of the edge-rooted unit, over every arc:
+ *   stats[0] = number of arcs (m)
+ *   stats[1] = sum over arcs of d->(u) + d->(v)
+ *   stats[2] = sum over arcs of s = |N->(u) cap N->(v)|   (= triangles)
+ *   stats[3] = sum over arcs of sum_{w in C_uv} d->(w)
+ *   stats[4] = max s
+ *   stats[5] = number of arcs with s >= k - 2   (the arcs that survive pruning)
+ *   stats[6] = sum over those arcs of d->(u) + d->(v)
+ *   stats[7] = sum over those arcs of s
+ *   stats[8] = sum over those arcs of sum_{w in C_uv} d->(w)
+ *   stats[9] = max out-degree
+ * hist (may be NULL): hist[b] = arcs with s in [2^(b-1), 2^b) for b >= 1,
+ *   hist[0] = arcs with s = 0; 33 entries. */
+int oracle_arc_stats(int32_t n, const int32_t* dptr, const int32_t* dcol, int32_t k,
+                     uint64_t* stats, uint64_t* hist)
+{
+    memset(stats, 0, sizeof(uint64_t) * 10);
+    if (hist) memset(hist, 0, sizeof(uint64_t) * 33);
+    int32_t mx = max_outdeg_of(n, dptr);
+    int32_t* cand = (int32_t*)malloc(sizeof(int32_t) * ((size_t)mx + 1));
+    if (!cand) return ORACLE_ENOMEM;
+    stats[9] = (uint64_t)mx;
+    for (int32_t u = 0; u < n; ++u) {
+        for (int64_t e = dptr[u]; e < dptr[u + 1]; ++e) {
+            int32_t v = dcol[e];
+            uint64_t duv = (uint64_t)(dptr[u + 1] - dptr[u]) + (uint64_t)(dptr[v + 1] - dptr[v]);
+            int64_t s = intersect(dcol + dptr[u], dptr[u + 1] - dptr[u],
+                                  dcol + dptr[v], dptr[v + 1] - dptr[v], cand);
+            uint64_t sumw = 0;
+            for (int64_t i = 0; i < s; ++i)
+                sumw += (uint64_t)(dptr[cand[i] + 1] - dptr[cand[i]]);
+            stats[0] += 1;
+            stats[1] += duv;
+            stats[2] += (uint64_t)s;
+            stats[3] += sumw;
+            if ((uint64_t)s > stats[4]) stats[4] = (uint64_t)s;
+            if (s >= k - 2) {
+                stats[5] += 1;
+                stats[6] += duv;
+                stats[7] += (uint64_t)s;
+                stats[8] += sumw;
+            }
+            if (hist) {
+                int b = 0;
+                while (b < 32 && ((int64_t)1 << b) <= s) ++b;
+                hist[b] += 1;
+            }
+        }
+    }
+    free(cand);
+    return ORACLE_OK;
+}

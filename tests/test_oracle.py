@@ -1,0 +1,275 @@
+"""Pins of the reference counter (oracle/) against facts fixed by the paper
+and by mathematics, never against the oracle itself:
+
+* the worked example of Fig. 1 (DAG, induced subgraph, counts, per arc);
+* brute-force subset enumeration on random small graphs (definition);
+* closed forms: complete, Turan, bipartite, grid, hypercube, wheel,
+  disjoint cliques, empty graphs;
+* triangles = trace(A^3)/6 computed by scipy sparse matrix products;
+* invariance of every count under vertex relabelling;
+* per-size visit counts equal to the counts at smaller k;
+* DAG invariants of the degree ordering (Section IV).
+"""
+import json
+import math
+import os
+from itertools import combinations
+
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+import graphgen as gg
+import oracle
+from tests._brute import brute_count, brute_rooted
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def ocount(g, k, prune=True):
+    c, ovf = oracle.count(g, k, prune=prune)
+    assert not ovf
+    return c
+
+
+# ------------------------------------------------------------------ Fig. 1
+
+@pytest.fixture(scope="module")
+def fig1():
+    with open(os.path.join(GOLDEN, "fig1.json")) as f:
+        return json.load(f)
+
+
+def test_fig1_graph_and_degrees(fig1):
+    g = gg.fig1_example()
+    assert g.n == fig1["n"] and g.m == len(fig1["edges"])
+    assert list(g.degrees()) == fig1["degrees"]
+
+
+def test_fig1_dag(fig1):
+    g = gg.fig1_example()
+    dptr, dcol = oracle.orient(g.n, g.row_ptr, g.col)
+    for u in range(g.n):
+        assert list(dcol[dptr[u]:dptr[u + 1]]) == fig1["dag_out_lists"][str(u)], u
+
+
+def test_fig1_subgraph_of_vertex0(fig1):
+    g = gg.fig1_example()
+    dptr, dcol = oracle.orient(g.n, g.row_ptr, g.col)
+    nu = list(dcol[dptr[0]:dptr[1]])
+    assert nu == fig1["subgraph_induced_by_0"]["vertices"]
+    arcs = []
+    for w in nu:
+        for x in dcol[dptr[w]:dptr[w + 1]]:
+            if x in nu:
+                arcs.append([w, int(x)])
+    assert sorted(arcs) == sorted(fig1["subgraph_induced_by_0"]["arcs"])
+
+
+def test_fig1_counts(fig1):
+    g = gg.fig1_example()
+    for k, want in fig1["clique_counts"].items():
+        assert ocount(g, int(k)) == want
+        assert ocount(g, int(k), prune=False) == want
+
+
+def test_fig1_per_arc(fig1):
+    g = gg.fig1_example()
+    dptr, dcol = oracle.orient(g.n, g.row_ptr, g.col)
+    src = np.repeat(np.arange(g.n), np.diff(dptr))
+    for k, key in ((3, "per_arc_k3"), (4, "per_arc_k4")):
+        got, _ = oracle.count_arcs(g.n, dptr, dcol, k, src, dcol)
+        table = {f"{u},{v}": int(c) for u, v, c in zip(src, dcol, got)}
+        for arc, want in fig1[key].items():
+            assert table[arc] == want, (k, arc)
+        assert sum(table.values()) == fig1["clique_counts"][str(k)]
+
+
+# ------------------------------------------------------------- brute force
+
+def _random_graphs(count, nmin, nmax, seed):
+    rng = np.random.default_rng(seed)
+    for i in range(count):
+        n = int(rng.integers(nmin, nmax + 1))
+        p = float(rng.uniform(0.2, 0.9))
+        iu, ju = np.triu_indices(n, 1)
+        keep = rng.random(iu.size) < p
+        yield gg.csr_from_edges(n, iu[keep], ju[keep], perm_seed=int(rng.integers(1 << 30)))
+
+
+@pytest.mark.parametrize("seed", [1, 2, 3])
+def test_brute_force_random(seed):
+    for g in _random_graphs(8, 1, 13, seed):
+        for k in range(1, 9):
+            assert ocount(g, k) == brute_count(g, k), (g.n, g.m, k)
+
+
+def test_brute_force_unpruned_and_rooted():
+    for g in _random_graphs(6, 5, 11, 7):
+        dptr, dcol = oracle.orient(g.n, g.row_ptr, g.col)
+        deg = g.degrees()
+
+        def less(a, b):
+            return deg[a] < deg[b] or (deg[a] == deg[b] and a < b)
+
+        src = np.repeat(np.arange(g.n), np.diff(dptr))
+        for k in range(2, 7):
+            assert ocount(g, k, prune=False) == brute_count(g, k)
+            got, _ = oracle.count_arcs(g.n, dptr, dcol, k, src, dcol)
+            for u, v, c in zip(src, dcol, got):
+                assert int(c) == brute_rooted(g, k, int(u), int(v), less)
+
+
+# ------------------------------------------------------------- closed forms
+
+@pytest.mark.parametrize("n", [1, 2, 5, 9, 13, 20])
+def test_complete(n):
+    g = gg.complete(n)
+    for k in range(1, min(n + 2, 12)):
+        assert ocount(g, k) == math.comb(n, k)
+
+
+def _elementary_symmetric(parts, k):
+    return sum(math.prod(c) for c in combinations(parts, k))
+
+
+@pytest.mark.parametrize("n,r", [(10, 3), (12, 4), (15, 5), (9, 2), (17, 6)])
+def test_turan(n, r):
+    g = gg.turan(n, r)
+    parts = [n // r + (1 if i < n % r else 0) for i in range(r)]
+    for k in range(2, r + 3):
+        assert ocount(g, k) == _elementary_symmetric(parts, k)
+
+
+def test_turan_quoted_values():
+    # T(10,3) with parts (4,3,3) and T(12,4) with parts (3,3,3,3)
+    assert [ocount(gg.turan(10, 3), k) for k in (2, 3, 4)] == [33, 36, 0]
+    assert [ocount(gg.turan(12, 4), k) for k in (2, 3, 4)] == [54, 108, 81]
+
+
+@pytest.mark.parametrize("g", [gg.complete_bipartite(5, 7), gg.grid(6, 5), gg.hypercube(5),
+                               gg.complete_bipartite(1, 9)])
+def test_bipartite_has_no_triangles(g):
+    assert ocount(g, 2) == g.m
+    for k in range(3, 7):
+        assert ocount(g, k) == 0
+
+
+@pytest.mark.parametrize("rim", [4, 5, 8, 13])
+def test_wheel(rim):
+    g = gg.wheel(rim)
+    assert ocount(g, 3) == rim
+    assert ocount(g, 4) == 0
+
+
+def test_wheel_rim3_is_k4():
+    assert [ocount(gg.wheel(3), k) for k in (3, 4, 5)] == [4, 1, 0]
+
+
+def test_disjoint_cliques():
+    sizes = [3, 7, 12, 5, 20, 1]
+    g = gg.disjoint_cliques(sizes)
+    for k in range(1, 10):
+        assert ocount(g, k) == sum(math.comb(s, k) for s in sizes)
+
+
+def test_empty():
+    g = gg.empty(10)
+    assert ocount(g, 1) == 10
+    for k in range(2, 6):
+        assert ocount(g, k) == 0
+    g0 = gg.empty(0)
+    assert ocount(g0, 1) == 0 and ocount(g0, 3) == 0
+
+
+# ------------------------------------------------------- library routine pin
+
+def _trace_triangles(g):
+    a = sp.csr_matrix((np.ones(g.nnz, dtype=np.int64), g.col, g.row_ptr), shape=(g.n, g.n))
+    return int((a @ a).multiply(a).sum()) // 6
+
+
+@pytest.mark.parametrize("g", [gg.rmat(10, 16, seed=3), gg.erdos_renyi(2000, 30, seed=4),
+                               gg.chung_lu(n=1 << 13, mean_degree=20, w_max=800, planted=20,
+                                           seed=5, clique_seed=6)])
+def test_triangles_equal_trace(g):
+    assert ocount(g, 3) == _trace_triangles(g)
+
+
+def test_triangles_rmat14_trace():
+    g = gg.config_graph("rmat14")
+    assert ocount(g, 3) == _trace_triangles(g)
+
+
+# --------------------------------------------------------------- invariants
+
+def test_relabel_invariance():
+    g = gg.rmat(9, 16, seed=11)
+    rng = np.random.default_rng(0)
+    perms = [rng.permutation(g.n), np.arange(g.n)[::-1].copy()]
+    for k in range(3, 7):
+        base = ocount(g, k)
+        for p in perms:
+            assert ocount(gg.relabel(g, p), k) == base
+
+
+def test_visits_are_smaller_counts():
+    g = gg.rmat(9, 16, seed=12)
+    k = 6
+    c, ovf, vis = oracle.count(g, k, prune=False, visits=True)
+    for j in range(1, k + 1):
+        assert vis[j] == ocount(g, j), j
+    assert vis[k] == c
+
+
+def test_pruning_preserves_counts():
+    g = gg.erdos_renyi(300, 25, seed=13)
+    for k in range(3, 8):
+        assert ocount(g, k, prune=True) == ocount(g, k, prune=False)
+
+
+def test_dag_invariants():
+    for g in (gg.rmat(11, 16, seed=14), gg.erdos_renyi(1000, 12, seed=15), gg.fig1_example()):
+        dptr, dcol = oracle.orient(g.n, g.row_ptr, g.col)
+        deg = g.degrees()
+        assert dptr[-1] == g.m
+        src = np.repeat(np.arange(g.n), np.diff(dptr))
+        # every edge once, in one direction, following omega
+        assert np.all((deg[src] < deg[dcol]) | ((deg[src] == deg[dcol]) & (src < dcol)))
+        s, d = g.edges()
+        und = set(zip(s.tolist(), d.tolist()))
+        arcs = set((min(a, b), max(a, b)) for a, b in zip(src.tolist(), dcol.tolist()))
+        assert arcs == und and len(arcs) == g.m
+        # rows ascending
+        for u in range(g.n):
+            row = dcol[dptr[u]:dptr[u + 1]]
+            assert np.all(np.diff(row) > 0)
+        # out-degree bound of the degree ordering: d->(u) <= floor(sqrt(2m))
+        assert np.diff(dptr).max(initial=0) <= math.isqrt(2 * g.m)
+
+
+def test_check_csr_rejects_defects():
+    g = gg.fig1_example()
+    assert oracle.check_csr(g.n, g.row_ptr, g.col)
+    bad = g.col.copy()
+    bad[0], bad[1] = bad[1], bad[0]          # unsorted row
+    assert not oracle.check_csr(g.n, g.row_ptr, bad)
+    bad = g.col.copy()
+    bad[0] = 0                               # self-loop at vertex 0
+    assert not oracle.check_csr(g.n, g.row_ptr, bad)
+
+
+# ------------------------------------------------------- a planted mistake
+
+def test_a_planted_mistake_is_caught():
+    """A counter that forgets the tie-break of the ordering counts some
+    cliques twice or never; the closed form on a regular graph catches it."""
+    g = gg.complete(6)                       # all degrees equal: only ids decide
+    dptr, dcol = oracle.orient(g.n, g.row_ptr, g.col)
+    # the wrong DAG keeps both directions of every tie
+    wrong_ptr = g.row_ptr.copy()
+    wrong_col = g.col.copy()
+    c_right, _ = oracle.count_dag(g.n, dptr, dcol, 3)
+    c_wrong, _ = oracle.count_dag(g.n, wrong_ptr, wrong_col, 3)
+    assert c_right == math.comb(6, 3)
+    assert c_wrong != math.comb(6, 3)
