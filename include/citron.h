@@ -1,0 +1,215 @@
+/*
+ * citron.h -- C ABI of libcitron, an exact k-clique counter for one AMD
+ * Instinct MI355X (gfx950).
+ *
+ * Method (Lonkar & Beamer, "Accelerating Clique Counting in Sparse
+ * Real-World Graphs via Communication-Reducing Optimizations"):
+ *   - ordering phase (Section IV, Algorithm 3): the undirected graph is
+ *     oriented into a DAG by the degree ordering: u -> v iff d(u) < d(v), or
+ *     d(u) == d(v) and u < v, where d is the undirected degree; out-lists
+ *     keep ascending vertex-id order;
+ *   - counting phase (Section III, Algorithm 2; Section V-B, Algorithm 5 and
+ *     its two heuristics): for every vertex u the subgraph induced on its
+ *     out-neighbours is built from sorted-list intersections, and the
+ *     (k-1)-cliques of that subgraph are counted by recursion; the last
+ *     level sums degrees only; subgraphs too small to hold the rest of a
+ *     clique are skipped.
+ *
+ * Conventions for every call:
+ *   - No call aborts or throws.  Each returns a citron_status (or writes one
+ *     through a status pointer); a human-readable reason for the last
+ *     failure on the calling thread is available from citron_last_error().
+ *   - Counts are uint64_t.  A count whose exact value is >= 2^64 is
+ *     returned modulo 2^64 with status CITRON_EOVERFLOW.  The flag does not
+ *     depend on the order of additions: with non-negative addends some
+ *     addition carries iff the exact total is >= 2^64.
+ *   - Vertex ids and CSR offsets are int32_t; the undirected CSR may hold at
+ *     most 2^31 - 1 entries (that is, fewer than 2^30 undirected edges).
+ *   - All device work runs on the stream the graph was loaded with.  Calls
+ *     that return results to the host synchronise that stream.
+ *   - Different graphs may be used from different host threads at once.  A
+ *     graph must not be freed while another thread uses it.  Count calls on
+ *     one graph from several threads are serialised by the library.
+ */
+#ifndef CITRON_H
+#define CITRON_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct citron_graph citron_graph;    /* opaque; owns its device memory */
+typedef struct citron_server citron_server;  /* opaque; borrows its graphs */
+typedef int32_t citron_status;
+
+enum {
+    CITRON_OK = 0,
+    CITRON_EINVAL = 1,    /* bad argument or malformed graph */
+    CITRON_ENOMEM = 2,    /* device or host allocation failed */
+    CITRON_EOVERFLOW = 3, /* exact count >= 2^64; value returned mod 2^64 */
+    CITRON_EDEVICE = 4,   /* a HIP runtime call failed */
+    CITRON_ESTATE = 5,    /* call not valid in the graph's current state */
+    CITRON_EBUSY = 6      /* server: no free slot or memory; request queued */
+};
+
+/* citron_load_csr flags */
+#define CITRON_DEVICE_PTRS 1u   /* row_ptr / col_idx are device pointers */
+
+/* Largest clique size accepted by the count calls. */
+#define CITRON_KMAX 32
+
+/* Tuning of the counting phase.  Every field only changes speed, never a
+ * count.  `size` must be sizeof(citron_tuning); a field left 0 takes the
+ * library default.  Ranges are checked (CITRON_EINVAL outside them). */
+typedef struct {
+    int32_t size;
+    int32_t wg_waves;        /* waves per workgroup of the count kernel: 1..8 */
+    int32_t blocks_per_cu;   /* persistent count workgroups per compute unit: 1..32 */
+    int32_t light_rows;      /* rows per workgroup item of the subgraph build
+                                (batches of vertices with out-degree <= 64):
+                                64..1024, a multiple of 64 */
+    int32_t flush_rows;      /* one-word subgraph rows a wave queues before it
+                                searches them: 64..256 */
+    int32_t build_blocks_per_cu; /* persistent build workgroups per compute
+                                unit: 1..16 */
+    int32_t reserved;        /* must be 0 */
+} citron_tuning;
+
+/* ------------------------------------------------------------- graphs */
+
+/* Load a simple undirected graph given as CSR and copy it to the device.
+ *   n        number of vertices, 0 <= n < 2^31
+ *   nnz      number of CSR entries = 2m (each undirected edge twice)
+ *   row_ptr  int32[n+1], row_ptr[0] = 0, non-decreasing, row_ptr[n] = nnz
+ *   col_idx  int32[nnz]; row u lists the neighbours of u strictly
+ *            ascending; no self-loops; the graph must be symmetric
+ *            (v in row u iff u in row v) -- the input of Section IV
+ *   flags    0: host pointers; CITRON_DEVICE_PTRS: device pointers
+ *   stream   hipStream_t used for all device work on this graph, NULL for
+ *            the default stream
+ *   out      receives the handle (state LOADED)
+ * The arrays are only read during the call; the library keeps its own
+ * copies.  Validation of every rule above runs on the device; a violation
+ * gives CITRON_EINVAL and no handle. */
+citron_status citron_load_csr(int32_t n, int64_t nnz, const int32_t* row_ptr,
+                              const int32_t* col_idx, uint32_t flags, void* stream,
+                              citron_graph** out);
+
+/* Ordering phase (Section IV, Algorithm 3): build the degree-ordered DAG on
+ * the device.  LOADED -> ORDERED; calling it again is a no-op. */
+citron_status citron_order(citron_graph* g);
+
+/* Counting phase: number of k-cliques of the graph, 1 <= k <= CITRON_KMAX.
+ * k = 1 gives n, k = 2 gives m.  Requires ORDERED (else CITRON_ESTATE).
+ * Returns 0 on error; on CITRON_EOVERFLOW returns the count mod 2^64.
+ * st may be NULL. */
+uint64_t citron_count(citron_graph* g, int32_t k, citron_status* st);
+
+/* As citron_count, and also writes per_arc[e] = the number of k-cliques
+ * whose two lowest vertices in the degree ordering are the endpoints of
+ * DAG arc e (the order of citron_get_dag), for 2 <= k <= CITRON_KMAX.
+ * per_arc is a device pointer to m uint64_t; the sum of per_arc is the
+ * count.  Each entry wraps mod 2^64 on its own. */
+uint64_t citron_count_per_arc(citron_graph* g, int32_t k, uint64_t* per_arc,
+                              citron_status* st);
+
+/* Many (graph, k) queries in one persistent launch, replayed from a
+ * captured HIP graph when the same query set is submitted again.  All
+ * graphs must be ORDERED and share one device.  counts and sts are host
+ * arrays of nq entries; sts may be NULL.  t may be NULL for the defaults.
+ * Returns CITRON_OK if every query succeeded, else the first failing
+ * status (the other queries still complete). */
+citron_status citron_count_batch(citron_graph* const* gs, const int32_t* ks, int32_t nq,
+                                 uint64_t* counts, citron_status* sts,
+                                 const citron_tuning* t);
+
+/* Copy the DAG to host memory: dag_ptr int32[n+1], dag_col int32[m], in
+ * the arc order of Algorithm 3 (rows by source id, each row ascending). */
+citron_status citron_get_dag(const citron_graph* g, int32_t* dag_ptr, int32_t* dag_col);
+
+/* Sizes of a graph.  Any output pointer may be NULL.  max_outdeg is -1
+ * before citron_order. */
+citron_status citron_graph_info(const citron_graph* g, int64_t* n, int64_t* m,
+                                int32_t* max_outdeg, int64_t* device_bytes);
+
+/* Per-graph tuning (copied).  NULL restores the defaults. */
+citron_status citron_set_tuning(citron_graph* g, const citron_tuning* t);
+citron_status citron_get_tuning(const citron_graph* g, citron_tuning* t);
+
+/* Work counters of one k, measured by an instrumented launch of the count
+ * kernel (not a timed path).  stats receives CITRON_NSTATS uint64:
+ *   [0] subgraphs built (vertices)       [1] rows built (arcs)
+ *   [2] out-list entries read by the build (sum over arcs u->v of d->(v))
+ *   [3] last-level AND+popcount row-word operations
+ *   [4] recursion nodes pushed
+ *   [5] bytes of the DAG read by the build: 4 (d->(u) + 2) per built
+ *       vertex + 4 (d->(v) + 2) per built arc
+ *   [6] search steps on multi-word masks (a whole wave per step)
+ *   [7] nodes compacted to one word per row   [8] rows they produced
+ *   [9] light-engine loop iterations (per wave)
+ *   [10] sum over those iterations of the lanes holding work, so that
+ *        [10] / (64 [9]) is the engine's lane occupancy
+ *   [11] units started by the light engine   [12] task-buffer flushes
+ *   [13] last-level candidates on multi-word masks   [14] light pops
+ *   [15] sum over the kernel's waves of their busy time, [16] earliest
+ *        wave start, [17] latest wave end, [18] number of waves; times in
+ *        ticks of the 100 MHz device wall clock, so that
+ *        1 - [15] / ([18] ([17] - [16])) is the idle-wave fraction
+ *   [19] heavy arcs searched from an LDS copy of their subgraph */
+#define CITRON_NSTATS 20
+citron_status citron_work_stats(citron_graph* g, int32_t k, uint64_t* stats);
+
+void citron_free(citron_graph* g);       /* NULL is a no-op */
+
+/* Reason for the last failure on this thread; valid until the next call. */
+const char* citron_last_error(void);
+
+/* Device properties used for scheduling: compute units, LDS bytes per
+ * workgroup, name (up to 63 chars + NUL).  Any pointer may be NULL. */
+citron_status citron_device_info(int32_t* cus, int32_t* lds_bytes, char* name64);
+
+/* ------------------------------------------------------------ serving */
+
+/* A request loop over resident graphs with continuous batching: requests
+ * that arrive while others run are admitted as soon as a slot and device
+ * memory are free, and share the running persistent kernel.  One server
+ * drives one device from one host thread of its own. */
+typedef struct {
+    uint64_t tag;        /* the caller's tag from citron_server_submit */
+    int32_t graph_id;
+    int32_t k;
+    uint64_t count;
+    citron_status status;
+    int32_t pad;
+    int64_t t_submit_ns; /* steady-clock timestamps, nanoseconds */
+    int64_t t_admit_ns;
+    int64_t t_done_ns;
+} citron_result;
+
+/* hbm_budget_bytes bounds the device scratch the server may hold for
+ * admitted requests; max_slots bounds the requests in flight (1..1024). */
+citron_server* citron_server_create(int64_t hbm_budget_bytes, int32_t max_slots,
+                                    const citron_tuning* t);
+/* Register an ORDERED graph (borrowed; must outlive the server). */
+citron_status citron_server_add_graph(citron_server* s, citron_graph* g, int32_t* graph_id);
+/* Queue a request; never blocks. */
+citron_status citron_server_submit(citron_server* s, int32_t graph_id, int32_t k,
+                                   uint64_t tag);
+/* Move up to max finished results into results[]; returns how many. */
+int32_t citron_server_poll(citron_server* s, citron_result* results, int32_t max);
+/* Requests submitted but not yet returned by poll. */
+int32_t citron_server_pending(citron_server* s);
+void citron_server_destroy(citron_server* s);
+
+/* ------------------------------------------------------------ testing */
+
+/* Test hook: the next count on g starts its accumulator at `base` instead
+ * of 0 (so that the overflow flag can be forced from the host). */
+citron_status citron_test_seed_accumulator(citron_graph* g, uint64_t base);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* CITRON_H */

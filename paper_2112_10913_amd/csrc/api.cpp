@@ -1,0 +1,665 @@
+// Host side of the libcitron C ABI (include/citron.h): graph handles,
+// validation, the ordering phase, schedules and single / per-arc counts.
+// Batched counts live in batch.cpp, the request server in server.cpp.
+#include "api_internal.h"
+
+#include <algorithm>
+#include <cstring>
+#include <string>
+
+using namespace citron;
+
+namespace citron {
+
+thread_local std::string g_last_error;
+
+citron_status fail(citron_status st, const std::string& msg)
+{
+    g_last_error = msg;
+    return st;
+}
+
+citron_status hip_fail(hipError_t e, const char* what)
+{
+    return fail(CITRON_EDEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+citron_tuning default_tuning()
+{
+    citron_tuning t;
+    t.size = sizeof(citron_tuning);
+    t.wg_waves = 4;
+    t.blocks_per_cu = 2;
+    t.light_rows = 256;
+    t.flush_rows = 192;
+    t.build_blocks_per_cu = 4;
+    t.reserved = 0;
+    return t;
+}
+
+citron_status resolve_tuning(const citron_tuning* in, citron_tuning* out)
+{
+    citron_tuning d = default_tuning();
+    if (!in) { *out = d; return CITRON_OK; }
+    if (in->size != (int32_t)sizeof(citron_tuning))
+        return fail(CITRON_EINVAL, "citron_tuning.size must be sizeof(citron_tuning)");
+    citron_tuning t = *in;
+    if (t.wg_waves == 0) t.wg_waves = d.wg_waves;
+    if (t.blocks_per_cu == 0) t.blocks_per_cu = d.blocks_per_cu;
+    if (t.light_rows == 0) t.light_rows = d.light_rows;
+    if (t.flush_rows == 0) t.flush_rows = d.flush_rows;
+    if (t.build_blocks_per_cu == 0) t.build_blocks_per_cu = d.build_blocks_per_cu;
+    if (t.wg_waves < 1 || t.wg_waves > 8) return fail(CITRON_EINVAL, "wg_waves must be in 1..8");
+    if (t.blocks_per_cu < 1 || t.blocks_per_cu > 32) return fail(CITRON_EINVAL, "blocks_per_cu must be in 1..32");
+    if (t.light_rows < 64 || t.light_rows > 1024 || t.light_rows % 64)
+        return fail(CITRON_EINVAL, "light_rows must be a multiple of 64 in 64..1024");
+    if (t.flush_rows < 64 || t.flush_rows > 256) return fail(CITRON_EINVAL, "flush_rows must be in 64..256");
+    if (t.build_blocks_per_cu < 1 || t.build_blocks_per_cu > 16)
+        return fail(CITRON_EINVAL, "build_blocks_per_cu must be in 1..16");
+    if (t.reserved != 0) return fail(CITRON_EINVAL, "citron_tuning.reserved must be 0");
+    *out = t;
+    return CITRON_OK;
+}
+
+int device_cus(int dev)
+{
+    static int cached[64] = {0};
+    if (dev >= 0 && dev < 64 && cached[dev]) return cached[dev];
+    int cus = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
+        cus = 256;
+    if (dev >= 0 && dev < 64) cached[dev] = cus;
+    return cus;
+}
+
+template <typename T>
+static citron_status dalloc(T** p, size_t count, int64_t* acct, const char* what)
+{
+    *p = nullptr;
+    if (count == 0) count = 1;
+    hipError_t e = hipMalloc((void**)p, sizeof(T) * count);
+    if (e != hipSuccess) {
+        *p = nullptr;
+        return fail(CITRON_ENOMEM, std::string("hipMalloc failed for ") + what + ": " + hipGetErrorString(e));
+    }
+    if (acct) *acct += (int64_t)(sizeof(T) * count);
+    return CITRON_OK;
+}
+
+template <typename T>
+static void dfree(T*& p)
+{
+    if (p) (void)hipFree((void*)p);
+    p = nullptr;
+}
+
+static void free_plan(citron_graph* g)
+{
+    dfree(g->pb.hist);
+    dfree(g->pb.hist_scan);
+    dfree(g->pb.order);
+    dfree(g->pb.light_deg);
+    dfree(g->pb.light_pre);
+    dfree(g->pb.batch_start);
+    dfree(g->pb.header);
+    g->plan_valid = false;
+}
+
+static void free_graph_memory(citron_graph* g)
+{
+    dfree(g->d_row_ptr);
+    dfree(g->d_col);
+    dfree(g->d_outdeg);
+    dfree(g->d_dag_ptr);
+    dfree(g->d_dag_col);
+    dfree(g->d_dag_src);
+    dfree(g->d_small);
+    dfree(g->d_scan_ws);
+    dfree(g->d_query);
+    dfree(g->d_scratch);
+    dfree(g->d_stats);
+    dfree(g->d_rows_off);
+    dfree(g->d_rows);
+    dfree(g->d_arc_c);
+    dfree(g->d_harcs);
+    dfree(g->d_hhist);
+    dfree(g->d_hscan);
+    dfree(g->d_hcur);
+    g->rows_valid = false;
+    free_plan(g);
+    if (g->h_small) (void)hipHostFree(g->h_small);
+    g->h_small = nullptr;
+}
+
+// Vertex schedule: vertices by out-degree (descending) and light batches of
+// about t.light_rows rows for the subgraph build.
+citron_status ensure_plan(citron_graph* g, const citron_tuning& t)
+{
+    if (g->plan_valid && g->plan_tuning.light_rows == t.light_rows) return CITRON_OK;
+    hipError_t e = hipSetDevice(g->device);
+    if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
+    const int32_t D = std::max(g->max_outdeg, 2);
+    if (!g->pb.order) {
+        int64_t* acct = &g->device_bytes;
+        citron_status st;
+        if ((st = dalloc(&g->pb.hist, (size_t)D + 2, acct, "plan")) ||
+            (st = dalloc(&g->pb.hist_scan, (size_t)D + 3, acct, "plan")) ||
+            (st = dalloc(&g->pb.order, (size_t)g->n + 1, acct, "plan")) ||
+            (st = dalloc(&g->pb.light_deg, (size_t)g->n + 1, acct, "plan")) ||
+            (st = dalloc(&g->pb.light_pre, (size_t)g->n + 2, acct, "plan")) ||
+            (st = dalloc(&g->pb.batch_start, (size_t)g->n + 2, acct, "plan")) ||
+            (st = dalloc(&g->pb.header, 1, acct, "plan")))
+            return st;
+    }
+    e = launch_plan(g->n, g->d_dag_ptr, g->max_outdeg, t.light_rows, 0, 1, g->pb, g->d_scan_ws, g->stream);
+    if (e != hipSuccess) return hip_fail(e, "plan kernels");
+    g->h_vscan.assign((size_t)D, 0);
+    e = hipMemcpyAsync(&g->h_small->plan, g->pb.header, sizeof(PlanHeader), hipMemcpyDeviceToHost, g->stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(g->h_vscan.data(), g->pb.hist_scan, sizeof(int32_t) * (size_t)D,
+                           hipMemcpyDeviceToHost, g->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(g->stream);
+    if (e != hipSuccess) return hip_fail(e, "plan");
+    g->plan = g->h_small->plan;
+    g->plan_tuning = t;
+    g->plan_valid = true;
+    return CITRON_OK;
+}
+
+// Subgraph rows of every vertex (Algorithm 5), per-arc |C_uv|, the triangle
+// count and the schedule of heavy arcs; built once per graph.
+citron_status ensure_rows(citron_graph* g)
+{
+    if (g->rows_valid) return CITRON_OK;
+    citron_status st = ensure_plan(g, g->tuning);
+    if (st) return st;
+    hipError_t e = hipSetDevice(g->device);
+    if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
+    if (g->max_outdeg > kMaxDeg)
+        return fail(CITRON_EINVAL, "out-degree above 4096 in the degree-ordered DAG is not supported");
+    const int32_t D = std::max(g->max_outdeg, 2);
+    hipStream_t s = g->stream;
+    int64_t* acct = &g->device_bytes;
+    if (!g->d_rows_off) {
+        if ((st = dalloc(&g->d_rows_off, (size_t)g->n + 1, acct, "row offsets")) ||
+            (st = dalloc(&g->d_arc_c, (size_t)g->m, acct, "arc sizes")) ||
+            (st = dalloc(&g->d_harcs, (size_t)g->m, acct, "heavy arcs")) ||
+            (st = dalloc(&g->d_hhist, (size_t)D + 1, acct, "arc histogram")) ||
+            (st = dalloc(&g->d_hscan, (size_t)D + 1, acct, "arc histogram")) ||
+            (st = dalloc(&g->d_hcur, (size_t)D + 1, acct, "arc histogram")))
+            return st;
+    }
+    // row offsets: exclusive scan of d(u) * W(u) (outdeg buffer as scratch)
+    e = launch_rows_len(g->n, g->d_dag_ptr, g->d_outdeg, s);
+    if (e == hipSuccess) e = scan_exclusive(g->d_outdeg, g->d_rows_off, g->n, g->d_scan_ws, s);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(&g->h_small->rows_total, g->d_rows_off + g->n, sizeof(int32_t),
+                           hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return hip_fail(e, "row offsets");
+    const int64_t words = g->h_small->rows_total;
+    if (words < 0) return fail(CITRON_EINVAL, "subgraph rows exceed 2^31 words");
+    if (!g->d_rows && (st = dalloc(&g->d_rows, (size_t)std::max<int64_t>(words, 1), acct, "subgraph rows")))
+        return st;
+    SmallDev* sd = g->d_small;
+    if ((e = launch_fill_u64(&sd->tri_acc, 0, 1, s)) != hipSuccess ||
+        (e = launch_fill_i32(&sd->tri_ovf, 0, 2, s)) != hipSuccess ||
+        (e = launch_fill_u64(sd->build_stats, 0, kNumStats, s)) != hipSuccess)
+        return hip_fail(e, "fill");
+    BuildParams P;
+    P.dag_ptr = g->d_dag_ptr;
+    P.dag_col = g->d_dag_col;
+    P.order = g->pb.order;
+    P.light_pre = g->pb.light_pre;
+    P.batch_start = g->pb.batch_start;
+    P.plan = g->plan;
+    P.max_deg = g->max_outdeg;
+    P.rows_off = g->d_rows_off;
+    P.rows = g->d_rows;
+    P.arc_c = g->d_arc_c;
+    P.tri_acc = &sd->tri_acc;
+    P.tri_ovf = &sd->tri_ovf;
+    P.item_ctr = &sd->build_ctr;
+    P.build_stats = sd->build_stats;
+    e = launch_build_rows(P, device_cus(g->device) * g->tuning.build_blocks_per_cu, s);
+    if (e != hipSuccess) return hip_fail(e, "subgraph build");
+    e = launch_harc_schedule(g->m, g->d_dag_ptr, g->d_dag_src, g->d_arc_c, D, g->d_hhist, g->d_hscan,
+                             g->d_hcur, g->d_harcs, g->d_scan_ws, s);
+    if (e != hipSuccess) return hip_fail(e, "arc schedule");
+    g->h_hscan.assign((size_t)D + 1, 0);
+    e = hipMemcpyAsync(g->h_hscan.data(), g->d_hscan, sizeof(int32_t) * ((size_t)D + 1), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(&g->h_small->tri_acc, &sd->tri_acc, sizeof(uint64_t) + sizeof(int32_t),
+                           hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(g->h_small->build_stats, sd->build_stats, sizeof(uint64_t) * kNumStats,
+                           hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return hip_fail(e, "subgraph build");
+    g->tri = g->h_small->tri_acc;
+    g->tri_ovf = g->h_small->tri_ovf != 0;
+    memcpy(g->build_stats, g->h_small->build_stats, sizeof(g->build_stats));
+    g->rows_valid = true;
+    return CITRON_OK;
+}
+
+// Device scratch for the count kernel of this graph (grows on demand).
+citron_status ensure_scratch(citron_graph* g, int64_t bytes)
+{
+    if (bytes <= g->scratch_bytes) return CITRON_OK;
+    dfree(g->d_scratch);
+    g->device_bytes -= g->scratch_bytes;
+    g->scratch_bytes = 0;
+    citron_status st = dalloc(&g->d_scratch, (size_t)((bytes + 7) / 8), &g->device_bytes, "count scratch");
+    if (st) return st;
+    g->scratch_bytes = bytes;
+    return CITRON_OK;
+}
+
+void count_items(const citron_graph* g, int32_t k, int32_t* n_harcs, int32_t* light_first, int32_t* n_lightv)
+{
+    const int32_t D = std::max(g->max_outdeg, 2);
+    const int32_t y = k - 2;   // |C_uv| needed by an arc
+    *n_harcs = (y >= 0 && y <= D) ? g->h_hscan[(size_t)(D - y)] : 0;
+    // vertices with out-degree >= x: h_vscan[D - x + 1] (x in 2..D)
+    auto at_least = [&](int32_t x) -> int32_t {
+        if (x > D) return 0;
+        if (x < 2) x = 2;
+        return g->h_vscan[(size_t)(D - x + 1)];
+    };
+    const int32_t n_heavy = at_least(kLightMaxDeg + 1);
+    const int32_t a = std::max(k - 1, 2);
+    *light_first = n_heavy;
+    *n_lightv = a > kLightMaxDeg ? 0 : at_least(a) - n_heavy;
+}
+
+QueryDesc make_query(const citron_graph* g, int32_t k, unsigned long long* acc, int32_t* ovf,
+                     unsigned long long* per_arc, unsigned long long* stats, int32_t item_begin)
+{
+    QueryDesc q;
+    memset(&q, 0, sizeof(q));
+    q.dag_ptr = g->d_dag_ptr;
+    q.dag_src = g->d_dag_src;
+    q.order = g->pb.order;
+    q.rows.rows_off = g->d_rows_off;
+    q.rows.rows = g->d_rows;
+    q.rows.arc_c = g->d_arc_c;
+    q.rows.harcs = g->d_harcs;
+    q.acc = acc;
+    q.overflow = ovf;
+    q.per_arc = per_arc;
+    q.stats = stats;
+    q.k = k;
+    count_items(g, k, &q.n_harcs, &q.light_first, &q.n_lightv);
+    q.item_begin = item_begin;
+    q.n_items = q.n_harcs + q.n_lightv;
+    return q;
+}
+
+// Validity of a count request; sets *trivial when the answer is known
+// without the kernel.
+citron_status check_count_args(const citron_graph* g, int32_t k, bool* trivial, uint64_t* value)
+{
+    *trivial = false;
+    *value = 0;
+    if (!g) return fail(CITRON_EINVAL, "graph is NULL");
+    if (k < 1 || k > CITRON_KMAX) return fail(CITRON_EINVAL, "k must be in 1..CITRON_KMAX");
+    if (g->state != 1) return fail(CITRON_ESTATE, "citron_order must be called before counting");
+    if (k == 1) { *trivial = true; *value = (uint64_t)g->n; return CITRON_OK; }
+    if (k == 2) { *trivial = true; *value = (uint64_t)g->m; return CITRON_OK; }
+    // a rooted k-clique needs a vertex with k-1 out-neighbours
+    if (k - 1 > g->max_outdeg) { *trivial = true; *value = 0; return CITRON_OK; }
+    if (g->max_outdeg > kMaxDeg)
+        return fail(CITRON_EINVAL, "out-degree above 4096 in the degree-ordered DAG is not supported");
+    return CITRON_OK;
+}
+
+// One query through the count kernel; synchronous on the graph's stream.
+static citron_status run_single(citron_graph* g, int32_t k, unsigned long long* per_arc, bool stats,
+                                uint64_t* out_count)
+{
+    std::lock_guard<std::mutex> lock(g->mu);
+    hipError_t e = hipSetDevice(g->device);
+    if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
+    citron_status st = ensure_rows(g);
+    if (st) return st;
+    const uint64_t seed = g->seed_pending ? g->seed_base : 0;
+    g->seed_pending = false;
+    hipStream_t s = g->stream;
+    if (stats) memset(g->h_small->stats, 0, sizeof(g->h_small->stats));
+    if (k == 3) {
+        // triangles: the popcounts of the rows, summed by the build
+        if (per_arc) {
+            e = launch_arc_c_to_u64(g->m, g->d_arc_c, per_arc, s);
+            if (e == hipSuccess) e = hipStreamSynchronize(s);
+            if (e != hipSuccess) return hip_fail(e, "per-arc copy");
+        }
+        const uint64_t c = seed + g->tri;
+        *out_count = c;
+        if (g->tri_ovf || c < seed) return fail(CITRON_EOVERFLOW, "count is >= 2^64; value is mod 2^64");
+        return CITRON_OK;
+    }
+    const citron_tuning& t = g->tuning;
+    const int wg = t.wg_waves;
+    const int32_t blocks = device_cus(g->device) * t.blocks_per_cu;
+    const int64_t swords = count_scratch_words(g->max_outdeg, k, wg);
+    st = ensure_scratch(g, swords * 8 * blocks);
+    if (st) return st;
+    if (stats && !g->d_stats) {
+        st = dalloc(&g->d_stats, kNumStats, &g->device_bytes, "stats");
+        if (st) return st;
+    }
+    SmallDev* sd = g->d_small;
+    if ((e = launch_fill_u64(&sd->acc, seed, 1, s)) != hipSuccess ||
+        (e = launch_fill_i32(&sd->overflow, 0, 1, s)) != hipSuccess ||
+        (e = launch_fill_i32(&sd->item_ctr, 0, 1, s)) != hipSuccess)
+        return hip_fail(e, "fill");
+    if (stats && ((e = launch_fill_u64(g->d_stats, 0, kNumStats, s)) != hipSuccess ||
+                  (e = launch_fill_u64(g->d_stats + kStatWaveFirst, ~0ull, 1, s)) != hipSuccess))
+        return hip_fail(e, "fill");
+    if (per_arc && (e = launch_fill_u64(per_arc, 0, g->m, s)) != hipSuccess) return hip_fail(e, "fill");
+    g->h_small->query = make_query(g, k, &sd->acc, &sd->overflow, per_arc, stats ? g->d_stats : nullptr, 0);
+    if (!g->d_query) {
+        st = dalloc(&g->d_query, 1, &g->device_bytes, "query");
+        if (st) return st;
+    }
+    e = hipMemcpyAsync(g->d_query, &g->h_small->query, sizeof(QueryDesc), hipMemcpyHostToDevice, s);
+    if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync(query)");
+    CountLaunch cl;
+    cl.queries = g->d_query;
+    cl.n_queries = 1;
+    cl.total_items = g->h_small->query.n_items;
+    cl.item_ctr = &sd->item_ctr;
+    cl.scratch = g->d_scratch;
+    cl.scratch_words = swords;
+    cl.max_k = k;
+    cl.blocks = blocks;
+    cl.wg_waves = wg;
+    cl.lds_bytes = count_lds_bytes(0, k, wg);
+    cl.flush_rows = t.flush_rows;
+    cl.stats = stats;
+    cl.per_arc = per_arc != nullptr;
+    e = launch_count(cl, s);
+    if (e != hipSuccess) return hip_fail(e, "count kernel launch");
+    e = hipMemcpyAsync(&g->h_small->acc, &sd->acc, sizeof(uint64_t) + sizeof(int32_t) * 2,
+                       hipMemcpyDeviceToHost, s);
+    if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync(result)");
+    if (stats) {
+        e = hipMemcpyAsync(g->h_small->stats, g->d_stats, sizeof(uint64_t) * kNumStats,
+                           hipMemcpyDeviceToHost, s);
+        if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync(stats)");
+    }
+    e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return hip_fail(e, "count kernel");
+    *out_count = g->h_small->acc;
+    if (g->h_small->overflow) return fail(CITRON_EOVERFLOW, "count is >= 2^64; value is mod 2^64");
+    return CITRON_OK;
+}
+
+}  // namespace citron
+
+// ====================================================================== ABI
+
+extern "C" {
+
+citron_status citron_load_csr(int32_t n, int64_t nnz, const int32_t* row_ptr, const int32_t* col_idx,
+                              uint32_t flags, void* stream, citron_graph** out)
+{
+    if (!out) return fail(CITRON_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (n < 0) return fail(CITRON_EINVAL, "n must be >= 0");
+    if (nnz < 0 || nnz > 0x7fffffffLL) return fail(CITRON_EINVAL, "nnz must be in 0..2^31-1");
+    if (nnz % 2) return fail(CITRON_EINVAL, "nnz must be even for a symmetric graph");
+    if (!row_ptr) return fail(CITRON_EINVAL, "row_ptr is NULL");
+    if (nnz > 0 && !col_idx) return fail(CITRON_EINVAL, "col_idx is NULL");
+    if (flags & ~CITRON_DEVICE_PTRS) return fail(CITRON_EINVAL, "unknown flags");
+    const bool dev_ptrs = (flags & CITRON_DEVICE_PTRS) != 0;
+
+    citron_graph* g = new (std::nothrow) citron_graph();
+    if (!g) return fail(CITRON_ENOMEM, "host allocation failed");
+    hipError_t e = hipGetDevice(&g->device);
+    if (e != hipSuccess) { delete g; return hip_fail(e, "hipGetDevice"); }
+    g->stream = (hipStream_t)stream;
+    g->n = n;
+    g->nnz = nnz;
+    g->m = nnz / 2;
+    g->tuning = default_tuning();
+    citron_status st;
+    int64_t* acct = &g->device_bytes;
+    if ((st = dalloc(&g->d_row_ptr, (size_t)n + 1, acct, "row_ptr")) ||
+        (st = dalloc(&g->d_col, (size_t)nnz, acct, "col_idx")) ||
+        (st = dalloc(&g->d_small, 1, acct, "counters"))) {
+        free_graph_memory(g);
+        delete g;
+        return st;
+    }
+    e = hipHostMalloc((void**)&g->h_small, sizeof(SmallHost), hipHostMallocDefault);
+    if (e != hipSuccess) { free_graph_memory(g); delete g; return fail(CITRON_ENOMEM, "hipHostMalloc"); }
+    memset(g->h_small, 0, sizeof(SmallHost));
+    const hipMemcpyKind kind = dev_ptrs ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
+    hipStream_t s = g->stream;
+    e = hipMemcpyAsync(g->d_row_ptr, row_ptr, sizeof(int32_t) * ((size_t)n + 1), kind, s);
+    if (e == hipSuccess && nnz > 0)
+        e = hipMemcpyAsync(g->d_col, col_idx, sizeof(int32_t) * (size_t)nnz, kind, s);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(g->h_small->ends, g->d_row_ptr, sizeof(int32_t), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(g->h_small->ends + 1, g->d_row_ptr + n, sizeof(int32_t), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) { free_graph_memory(g); delete g; return hip_fail(e, "copying the CSR"); }
+    if (g->h_small->ends[0] != 0 || g->h_small->ends[1] != nnz) {
+        free_graph_memory(g);
+        delete g;
+        return fail(CITRON_EINVAL, "row_ptr[0] must be 0 and row_ptr[n] must equal nnz");
+    }
+    // device-side validation: offsets first (so that rows are in range), then entries
+    for (int stage = 0; stage < 2; ++stage) {
+        int32_t* err = &g->d_small->err;
+        e = launch_fill_i32(err, 0, 1, s);
+        if (e == hipSuccess) e = launch_validate(n, nnz, g->d_row_ptr, g->d_col, err, stage, s);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(&g->h_small->err, err, sizeof(int32_t), hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        if (e != hipSuccess) { free_graph_memory(g); delete g; return hip_fail(e, "validation"); }
+        const int32_t bits = g->h_small->err;
+        if (bits) {
+            std::string why;
+            if (bits & 1) why += " row_ptr not non-decreasing within [0, nnz];";
+            if (bits & 2) why += " column id out of range;";
+            if (bits & 4) why += " self-loop;";
+            if (bits & 8) why += " row not strictly ascending (unsorted or duplicate);";
+            if (bits & 16) why += " graph not symmetric;";
+            free_graph_memory(g);
+            delete g;
+            return fail(CITRON_EINVAL, "invalid CSR:" + why);
+        }
+    }
+    *out = g;
+    return CITRON_OK;
+}
+
+citron_status citron_order(citron_graph* g)
+{
+    if (!g) return fail(CITRON_EINVAL, "graph is NULL");
+    std::lock_guard<std::mutex> lock(g->mu);
+    if (g->state == 1) return CITRON_OK;
+    hipError_t e = hipSetDevice(g->device);
+    if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
+    int64_t* acct = &g->device_bytes;
+    citron_status st;
+    g->scan_ws_ints = scan_workspace_ints((int64_t)g->n + 1) + 64;
+    if ((st = dalloc(&g->d_outdeg, (size_t)g->n + 1, acct, "outdeg")) ||
+        (st = dalloc(&g->d_dag_ptr, (size_t)g->n + 1, acct, "dag_ptr")) ||
+        (st = dalloc(&g->d_dag_col, (size_t)g->m, acct, "dag_col")) ||
+        (st = dalloc(&g->d_dag_src, (size_t)g->m, acct, "dag_src")) ||
+        (st = dalloc(&g->d_scan_ws, g->scan_ws_ints, acct, "scan workspace")))
+        return st;
+    hipStream_t s = g->stream;
+    int32_t* mx = &g->d_small->max_outdeg;
+    e = launch_fill_i32(mx, 0, 1, s);
+    if (e == hipSuccess)
+        e = launch_orient(g->n, g->d_row_ptr, g->d_col, g->d_outdeg, g->d_dag_ptr, g->d_dag_col,
+                          g->d_dag_src, mx, g->d_scan_ws, s);
+    if (e == hipSuccess && g->n == 0) e = launch_fill_i32(g->d_dag_ptr, 0, 1, s);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(&g->h_small->max_outdeg, mx, sizeof(int32_t), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(g->h_small->ends, g->d_dag_ptr + g->n, sizeof(int32_t), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return hip_fail(e, "ordering kernels");
+    if (g->h_small->ends[0] != g->m) return fail(CITRON_EDEVICE, "ordering produced a wrong arc count");
+    g->max_outdeg = g->h_small->max_outdeg;
+    g->state = 1;
+    // the schedule of the counting phase is part of ordering the graph
+    return ensure_plan(g, g->tuning);
+}
+
+uint64_t citron_count(citron_graph* g, int32_t k, citron_status* st_out)
+{
+    citron_status dummy;
+    citron_status* st = st_out ? st_out : &dummy;
+    bool trivial;
+    uint64_t v;
+    *st = check_count_args(g, k, &trivial, &v);
+    if (*st) return 0;
+    if (trivial) return v;
+    uint64_t c = 0;
+    *st = run_single(g, k, nullptr, false, &c);
+    if (*st && *st != CITRON_EOVERFLOW) return 0;
+    return c;
+}
+
+uint64_t citron_count_per_arc(citron_graph* g, int32_t k, uint64_t* per_arc, citron_status* st_out)
+{
+    citron_status dummy;
+    citron_status* st = st_out ? st_out : &dummy;
+    if (k < 2) { *st = fail(CITRON_EINVAL, "per-arc counts need k >= 2"); return 0; }
+    if (!per_arc && g && g->m > 0) { *st = fail(CITRON_EINVAL, "per_arc is NULL"); return 0; }
+    bool trivial;
+    uint64_t v;
+    *st = check_count_args(g, k, &trivial, &v);
+    if (*st) return 0;
+    if (trivial) {
+        std::lock_guard<std::mutex> lock(g->mu);
+        hipError_t e = launch_fill_u64((unsigned long long*)per_arc, k == 2 ? 1ull : 0ull, g->m, g->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(g->stream);
+        if (e != hipSuccess) { *st = hip_fail(e, "fill"); return 0; }
+        return v;
+    }
+    uint64_t c = 0;
+    *st = run_single(g, k, (unsigned long long*)per_arc, false, &c);
+    if (*st && *st != CITRON_EOVERFLOW) return 0;
+    return c;
+}
+
+citron_status citron_work_stats(citron_graph* g, int32_t k, uint64_t* stats)
+{
+    if (!stats) return fail(CITRON_EINVAL, "stats is NULL");
+    memset(stats, 0, sizeof(uint64_t) * CITRON_NSTATS);
+    bool trivial;
+    uint64_t v;
+    citron_status st = check_count_args(g, k, &trivial, &v);
+    if (st) return st;
+    if (trivial) return CITRON_OK;
+    uint64_t c = 0;
+    st = run_single(g, k, nullptr, true, &c);
+    if (st && st != CITRON_EOVERFLOW) return st;
+    memcpy(stats, g->h_small->stats, sizeof(uint64_t) * CITRON_NSTATS);
+    stats[kStatVertices] = g->build_stats[kStatVertices];
+    stats[kStatRows] = g->build_stats[kStatRows];
+    stats[kStatEntries] = g->build_stats[kStatEntries];
+    stats[kStatBytes] = g->build_stats[kStatBytes];
+    return CITRON_OK;
+}
+
+citron_status citron_get_dag(const citron_graph* g, int32_t* dag_ptr, int32_t* dag_col)
+{
+    if (!g) return fail(CITRON_EINVAL, "graph is NULL");
+    if (g->state != 1) return fail(CITRON_ESTATE, "citron_order must be called first");
+    if (!dag_ptr || (g->m > 0 && !dag_col)) return fail(CITRON_EINVAL, "output pointer is NULL");
+    citron_graph* gm = const_cast<citron_graph*>(g);
+    std::lock_guard<std::mutex> lock(gm->mu);
+    hipError_t e = hipSetDevice(g->device);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(dag_ptr, g->d_dag_ptr, sizeof(int32_t) * ((size_t)g->n + 1),
+                           hipMemcpyDeviceToHost, g->stream);
+    if (e == hipSuccess && g->m > 0)
+        e = hipMemcpyAsync(dag_col, g->d_dag_col, sizeof(int32_t) * (size_t)g->m, hipMemcpyDeviceToHost,
+                           g->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(g->stream);
+    if (e != hipSuccess) return hip_fail(e, "copying the DAG");
+    return CITRON_OK;
+}
+
+citron_status citron_graph_info(const citron_graph* g, int64_t* n, int64_t* m, int32_t* max_outdeg,
+                                int64_t* device_bytes)
+{
+    if (!g) return fail(CITRON_EINVAL, "graph is NULL");
+    if (n) *n = g->n;
+    if (m) *m = g->m;
+    if (max_outdeg) *max_outdeg = g->state == 1 ? g->max_outdeg : -1;
+    if (device_bytes) *device_bytes = g->device_bytes;
+    return CITRON_OK;
+}
+
+citron_status citron_set_tuning(citron_graph* g, const citron_tuning* t)
+{
+    if (!g) return fail(CITRON_EINVAL, "graph is NULL");
+    citron_tuning r;
+    citron_status st = resolve_tuning(t, &r);
+    if (st) return st;
+    std::lock_guard<std::mutex> lock(g->mu);
+    g->tuning = r;
+    return CITRON_OK;
+}
+
+citron_status citron_get_tuning(const citron_graph* g, citron_tuning* t)
+{
+    if (!g || !t) return fail(CITRON_EINVAL, "NULL argument");
+    *t = g->tuning;
+    return CITRON_OK;
+}
+
+void citron_free(citron_graph* g)
+{
+    if (!g) return;
+    batch_forget_graph(g);
+    {
+        std::lock_guard<std::mutex> lock(g->mu);
+        (void)hipSetDevice(g->device);
+        if (g->stream) (void)hipStreamSynchronize(g->stream);
+        else (void)hipDeviceSynchronize();
+        free_graph_memory(g);
+    }
+    delete g;
+}
+
+const char* citron_last_error(void) { return g_last_error.c_str(); }
+
+citron_status citron_device_info(int32_t* cus, int32_t* lds_bytes, char* name64)
+{
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    hipDeviceProp_t p;
+    e = hipGetDeviceProperties(&p, dev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDeviceProperties");
+    if (cus) *cus = p.multiProcessorCount;
+    if (lds_bytes) *lds_bytes = (int32_t)p.sharedMemPerBlock;
+    if (name64) {
+        strncpy(name64, p.gcnArchName, 63);
+        name64[63] = 0;
+    }
+    return CITRON_OK;
+}
+
+citron_status citron_test_seed_accumulator(citron_graph* g, uint64_t base)
+{
+    if (!g) return fail(CITRON_EINVAL, "graph is NULL");
+    std::lock_guard<std::mutex> lock(g->mu);
+    g->seed_base = base;
+    g->seed_pending = true;
+    return CITRON_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,84 @@
+// Internal declarations shared by the HIP kernels and the host side of
+// libcitron.  Not part of the public ABI (include/citron.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace citron {
+
+constexpr int kWave = 64;            // gfx950 wavefront width
+constexpr int kLightMaxDeg = 64;     // out-degree that fits one 64-bit row word
+constexpr int kMaxWords = 64;        // row words per subgraph (out-degree <= 4096)
+constexpr int kMaxDeg = kMaxWords * 64;
+constexpr int kKMax = 32;
+
+// Count-kernel statistics slots (citron_work_stats).
+enum StatSlot {
+    kStatVertices = 0,     // subgraphs built
+    kStatRows = 1,         // rows built (arcs)
+    kStatEntries = 2,      // out-list entries read by the build
+    kStatWordOps = 3,      // last-level AND+popcount row-word operations
+    kStatPushes = 4,       // recursion nodes pushed (both engines)
+    kStatBytes = 5,        // DAG bytes read by the build
+    kStatHeavySteps = 6,   // wave-uniform search steps on multi-word masks
+    kStatCompactions = 7,  // nodes compacted to one word per row
+    kStatCompactRows = 8,  // rows written by compaction
+    kStatLightIters = 9,   // light-engine loop iterations (per wave)
+    kStatLightActive = 10, // sum over those iterations of lanes with a unit
+    kStatLightUnits = 11,  // units started by the light engine
+    kStatFlushes = 12,     // task-buffer flushes
+    kStatHeavyLeafCand = 13, // last-level candidates handled on multi-word masks
+    kStatLightPops = 14,   // light-engine pops
+    kStatWaveBusy = 15,    // sum over waves of (last item done - first item taken), wall-clock ticks
+    kStatWaveFirst = 16,   // earliest start of a wave (wall-clock ticks, atomic min)
+    kStatWaveLast = 17,    // latest end of a wave (atomic max)
+    kStatWaves = 18,       // waves that ran
+    kStatArcLds = 19,      // heavy arcs searched from an LDS copy of their subgraph
+    kNumStats = 20
+};
+
+// Schedule of one graph for the count kernel: vertices sorted by out-degree
+// (descending), the heavy prefix processed one vertex per workgroup (the
+// first n_split of them shared by split_factor workgroups), the light rest
+// grouped into batches of about light_rows rows.
+struct PlanHeader {
+    int32_t n_heavy;      // vertices with out-degree > kLightMaxDeg
+    int32_t n_split;      // heavy vertices shared by several workgroups
+    int32_t split_factor;
+    int32_t n_light;      // vertices with 2 <= out-degree <= kLightMaxDeg
+    int32_t n_batches;
+    int32_t n_items;      // n_split * split_factor + (n_heavy - n_split) + n_batches
+    int32_t light_rows;
+    int32_t max_rows;     // largest number of rows of one light batch
+};
+
+// Subgraph rows of one graph, built once (they do not depend on k): for
+// every vertex u with out-list v_0 < ... < v_{d-1}, row i is the bitmap over
+// positions 0..d-1 of N->(u) of N->(v_i) cap N->(u), W(u) = ceil(d/64) words.
+struct RowsDev {
+    const int32_t* rows_off;        // n + 1: first word of u's rows (< 2^31 words)
+    const unsigned long long* rows; // all rows
+    const int32_t* arc_c;           // m: popcount of arc e's row = |C_uv|
+    const int32_t* harcs;           // arcs of heavy vertices by |C_uv| descending
+};
+
+// One query of the count kernel (a (graph, k) pair).
+struct QueryDesc {
+    const int32_t* dag_ptr;
+    const int32_t* dag_src;      // source vertex of every arc
+    const int32_t* order;        // vertices by out-degree descending
+    RowsDev rows;
+    unsigned long long* acc;     // count accumulator
+    int32_t* overflow;           // set to 1 when an addition carried
+    unsigned long long* per_arc; // optional per-arc counts (nullptr: off)
+    unsigned long long* stats;   // optional work counters (nullptr: off)
+    int32_t k;
+    int32_t n_harcs;             // heavy arcs with |C_uv| >= k - 2 (a prefix of harcs)
+    int32_t light_first;         // index in order of the first light vertex
+    int32_t n_lightv;            // light vertices with out-degree >= k - 1
+    int32_t item_begin;          // first global item of this query
+    int32_t n_items;             // n_harcs + n_lightv
+};
+
+}  // namespace citron

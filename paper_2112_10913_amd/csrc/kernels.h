@@ -1,0 +1,78 @@
+// Launch wrappers of the HIP kernels of libcitron (host-callable).
+#pragma once
+
+#include "internal.h"
+
+namespace citron {
+
+// ---- ordering phase (kernels_order.hip)
+size_t scan_workspace_ints(int64_t n);
+hipError_t scan_exclusive(const int32_t* in, int32_t* out, int64_t n, int32_t* ws, hipStream_t s);
+hipError_t launch_validate(int32_t n, int64_t nnz, const int32_t* row_ptr, const int32_t* col,
+                           int32_t* err, int stage, hipStream_t s);
+hipError_t launch_orient(int32_t n, const int32_t* row_ptr, const int32_t* col, int32_t* outdeg,
+                         int32_t* dag_ptr, int32_t* dag_col, int32_t* dag_src, int32_t* max_outdeg,
+                         int32_t* scan_ws, hipStream_t s);
+
+// ---- vertex schedule (kernels_count.hip)
+struct PlanBuffers {
+    int32_t* hist;         // max_outdeg + 2
+    int32_t* hist_scan;    // max_outdeg + 3
+    int32_t* order;        // n
+    int32_t* light_deg;    // n
+    int32_t* light_pre;    // n + 1
+    int32_t* batch_start;  // n + 1
+    PlanHeader* header;    // device
+};
+hipError_t launch_plan(int32_t n, const int32_t* dag_ptr, int32_t max_outdeg, int32_t light_rows,
+                       int32_t split_min_deg, int32_t split_factor, const PlanBuffers& pb,
+                       int32_t* scan_ws, hipStream_t s);
+hipError_t launch_fill_i32(int32_t* p, int32_t v, int64_t n, hipStream_t s);
+hipError_t launch_fill_u64(unsigned long long* p, unsigned long long v, int64_t n, hipStream_t s);
+
+// ---- subgraph rows (kernels_rows.hip)
+struct BuildParams {
+    const int32_t* dag_ptr;
+    const int32_t* dag_col;
+    const int32_t* order;
+    const int32_t* light_pre;
+    const int32_t* batch_start;
+    PlanHeader plan;
+    int32_t max_deg;
+    const int32_t* rows_off;
+    unsigned long long* rows;
+    int32_t* arc_c;
+    unsigned long long* tri_acc;       // triangles (the k = 3 count)
+    int32_t* tri_ovf;
+    int32_t* item_ctr;
+    unsigned long long* build_stats;   // kNumStats slots
+};
+int32_t build_lds_bytes(int32_t light_rows, int32_t max_deg);
+hipError_t launch_rows_len(int32_t n, const int32_t* dag_ptr, int32_t* len, hipStream_t s);
+hipError_t launch_build_rows(const BuildParams& P, int32_t blocks, hipStream_t s);
+hipError_t launch_harc_schedule(int64_t m, const int32_t* dag_ptr, const int32_t* dag_src, const int32_t* arc_c,
+                                int32_t D, int32_t* hist, int32_t* hscan, int32_t* cursor, int32_t* harcs,
+                                int32_t* scan_ws, hipStream_t s);
+hipError_t launch_arc_c_to_u64(int64_t m, const int32_t* arc_c, unsigned long long* out, hipStream_t s);
+
+// ---- counting phase (kernels_count.hip)
+struct CountLaunch {
+    const QueryDesc* queries;   // device table
+    int32_t n_queries;
+    int32_t total_items;
+    int32_t* item_ctr;          // device, zeroed by the launch sequence
+    unsigned long long* scratch;   // stacks of k > 12, scratch_words per block
+    int64_t scratch_words;
+    int32_t max_k;
+    int32_t blocks;
+    int32_t wg_waves;
+    int32_t lds_bytes;          // dynamic LDS per block
+    int32_t flush_rows;
+    bool stats;                 // instrumented launch
+    bool per_arc;               // some query writes per-arc counts
+};
+int64_t count_scratch_words(int32_t max_deg, int32_t max_k, int32_t wg_waves);
+int32_t count_lds_bytes(int32_t light_rows, int32_t max_k, int32_t wg_waves);
+hipError_t launch_count(const CountLaunch& cl, hipStream_t s);
+
+}  // namespace citron
