@@ -105,8 +105,9 @@ def main():
             counts[k] = h.count_checked(k)
             b.record()
             ev[k] = (a, b)
-            if record:
-                log(f"  k={k} count={counts[k][0]} overflow={counts[k][1]}")
+            b.synchronize()
+            log(f"  k={k} count={counts[k][0]} overflow={counts[k][1]} "
+                f"{a.elapsed_time(b):.1f} ms")
         return h, counts, ev
 
     for i in range(args.warmup):

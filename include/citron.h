@@ -188,8 +188,12 @@ typedef struct {
     int64_t t_done_ns;
 } citron_result;
 
-/* hbm_budget_bytes bounds the device scratch the server may hold for
- * admitted requests; max_slots bounds the requests in flight (1..1024). */
+/* hbm_budget_bytes bounds the device memory the server may hold for
+ * admitted requests beyond their resident graphs: a request holds its
+ * descriptor and accumulator (a few hundred bytes) and, for k > 12, its
+ * share of the search stacks kept in device memory.  A request that can
+ * never fit is returned with CITRON_ENOMEM; one that does not fit now waits.
+ * max_slots bounds the requests in flight (1..1024). */
 citron_server* citron_server_create(int64_t hbm_budget_bytes, int32_t max_slots,
                                     const citron_tuning* t);
 /* Register an ORDERED graph (borrowed; must outlive the server). */

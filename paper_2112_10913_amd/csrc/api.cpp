@@ -343,7 +343,7 @@ static citron_status run_single(citron_graph* g, int32_t k, unsigned long long* 
     const int wg = t.wg_waves;
     const int32_t blocks = device_cus(g->device) * t.blocks_per_cu;
     const int64_t swords = count_scratch_words(g->max_outdeg, k, wg);
-    st = ensure_scratch(g, swords * 8 * blocks);
+    st = ensure_scratch(g, std::max<int64_t>(swords * 8 * blocks, 8));
     if (st) return st;
     if (stats && !g->d_stats) {
         st = dalloc(&g->d_stats, kNumStats, &g->device_bytes, "stats");

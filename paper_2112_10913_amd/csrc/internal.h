@@ -78,7 +78,9 @@ struct QueryDesc {
     int32_t light_first;         // index in order of the first light vertex
     int32_t n_lightv;            // light vertices with out-degree >= k - 1
     int32_t item_begin;          // first global item of this query
-    int32_t n_items;             // n_harcs + n_lightv
+    int32_t n_items;             // items of this query in the launch
+    int32_t item_lo;             // local index of the query's first item in the launch
+    int32_t pad;
 };
 
 }  // namespace citron

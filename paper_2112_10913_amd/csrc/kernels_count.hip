@@ -161,7 +161,7 @@ int32_t count_lds_bytes(int32_t, int32_t max_k, int32_t wg_waves)
 
 int64_t count_scratch_words(int32_t, int32_t max_k, int32_t wg_waves)
 {
-    if (stack_in_lds(max_k)) return 32;
+    if (stack_in_lds(max_k)) return 0;
     return ((int64_t)wg_waves * wave_stack_words(max_k) + 31) & ~31ll;
 }
 
@@ -547,7 +547,7 @@ __global__ void __launch_bounds__(kMaxBlock) count_kernel(KParams P)
             cur = qi;
             per_arc = q.per_arc;
         }
-        const int i = g - q.item_begin;
+        const int i = q.item_lo + (g - q.item_begin);
         const int k = q.k;
         if (i < q.n_harcs) {
             const int e = q.rows.harcs[i];
