@@ -35,7 +35,8 @@ enum StatSlot {
     kStatWaveLast = 17,    // latest end of a wave (atomic max)
     kStatWaves = 18,       // waves that ran
     kStatArcLds = 19,      // heavy arcs searched from an LDS copy of their subgraph
-    kNumStats = 20
+    kStatNeed3Lanes = 20,  // children handled whole by one lane (two levels left)
+    kNumStats = 21
 };
 
 // Schedule of one graph for the count kernel: vertices sorted by out-degree

@@ -37,6 +37,7 @@ constexpr int kWaveBufRows = 256;       // one-word rows queued per wave
 constexpr int kLdsStackLevels = 8;      // deeper stacks (k > 12) live in device memory
 constexpr int kArcMaxC = 256;           // heavy arcs with |C_uv| <= this are copied to LDS
 constexpr int kArcWords = kArcMaxC * (kArcMaxC / 64);   // 8 KB per wave
+constexpr int kLaneMaxWords = 4;        // multi-word masks a lane holds in registers
 
 // ------------------------------------------------------------------ helpers
 
@@ -311,9 +312,54 @@ struct HeavyCtx {
 // Handle a node with mask m (c candidates, `need` more vertices to choose).
 // Returns true when the caller must search it depth first (c > 64 and
 // need >= 3).
-template <bool kStats, bool kPerArc>
-__device__ __forceinline__ bool heavy_node(const HeavyCtx& H, u64 m, int c, int need, WaveBuf& wb, Acc& A,
-                                           u64& uacc, u64* per_arc)
+template <bool kStats, bool kPerArc, bool kGlobal>
+__device__ __forceinline__ void heavy_dfs(const HeavyCtx& H, u64 M, int need0, int lvl0, WaveBuf& wb, Acc& A,
+                                          u64& uacc, u64* per_arc);
+
+// Copy the subgraph induced on the c candidates of m (rows in H, device
+// memory) to the wave's LDS buffer, compacted to W2 = ceil(c/64) words per
+// row: lane a rebuilds row a by extracting, word by word, the bits at the
+// candidates' positions.  c <= kArcMaxC.
+__device__ __forceinline__ int copy_to_lds(const HeavyCtx& H, u64 M, int c, u64* __restrict__ dst)
+{
+    const int q = lane_of();
+    const int W2 = (c + 63) >> 6;
+    for (int a0 = 0; a0 < c; a0 += kWave) {
+        const int a = a0 + q;
+        const int xa = wave_select(M, a, H.W);
+        const u64* __restrict__ src = H.rows + (int64_t)(a < c ? xa : 0) * H.W;
+        unsigned o[8] = {0u, 0u, 0u, 0u, 0u, 0u, 0u, 0u};
+        int b = 0;
+        for (int w = 0; w < H.W; ++w) {
+            u64 mw = readlane64(M, w);
+            if (mw == 0ull) continue;
+            const u64 word = a < c ? src[w] : 0ull;
+            const unsigned wlo = (unsigned)word, whi = (unsigned)(word >> 32);
+            while (mw) {
+                const int p = __builtin_ctzll(mw);
+                mw &= mw - 1;
+                const unsigned bit = ((p < 32 ? wlo : whi) >> (p & 31)) & 1u;
+#pragma unroll
+                for (int h = 0; h < 8; ++h)
+                    if ((b >> 5) == h) o[h] |= bit << (b & 31);
+                ++b;
+            }
+        }
+        if (a < c)
+            for (int i = 0; i < W2; ++i) dst[a * W2 + i] = ((u64)o[2 * i + 1] << 32) | o[2 * i];
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    return W2;
+}
+
+// Handle a node with mask m (c candidates, `need` more vertices to choose;
+// rows in device memory when kGlobal, else in the wave's LDS copy).  Returns
+// true when the caller must search it depth first.  lvl is the first free
+// level of the heavy stacks.
+template <bool kStats, bool kPerArc, bool kGlobal>
+__device__ __forceinline__ bool heavy_node(const HeavyCtx& H, u64 m, int c, int need, int lvl, WaveBuf& wb,
+                                           Acc& A, u64& uacc, u64* per_arc)
 {
     const int lane = lane_of();
     if (c < need) return false;
@@ -341,6 +387,62 @@ __device__ __forceinline__ bool heavy_node(const HeavyCtx& H, u64 m, int c, int 
                 A.st[kStatHeavyLeafCand] += 1;
             }
         }
+        return false;
+    }
+    if (need == 3 && c > kWave && H.W <= kLaneMaxWords) {
+        // two levels left, many candidates: lane j takes the j-th candidate
+        // x, forms its child mask m AND row_x (at most 4 words, in
+        // registers) and sums the last level of that child itself
+        for (int j0 = 0; j0 < c; j0 += kWave) {
+            const int j = j0 + lane;
+            const int x = wave_select(m, j, H.W);
+            u64 ch[kLaneMaxWords];
+            const u64* __restrict__ rx = H.rows + (int64_t)(j < c ? x : 0) * H.W;
+#pragma unroll
+            for (int w = 0; w < kLaneMaxWords; ++w) {
+                ch[w] = 0ull;
+                if (w < H.W) {
+                    const u64 mw = readlane64(m, w);
+                    if (j < c) ch[w] = mw & rx[w];
+                }
+            }
+            u64 s = 0;
+            u64 ops = 0;
+#pragma unroll
+            for (int w = 0; w < kLaneMaxWords; ++w) {
+                if (w >= H.W) break;
+                u64 r = ch[w];
+                while (r != 0ull) {
+                    const int y = w * 64 + __builtin_ctzll(r);
+                    r &= r - 1;
+                    const u64* __restrict__ ry = H.rows + (int64_t)y * H.W;
+                    int cnt = 0;
+#pragma unroll
+                    for (int i = 0; i < kLaneMaxWords; ++i)
+                        if (i < H.W) cnt += __popcll(ch[i] & ry[i]);
+                    s += (u64)cnt;
+                    if (kStats) ops += H.W;
+                }
+            }
+            A.acc += s;
+            if (kPerArc) uacc += s;
+            if (kStats) {
+                A.st[kStatWordOps] += ops;
+                if (j < c) A.st[kStatNeed3Lanes] += 1;
+            }
+        }
+        return false;
+    }
+    if (kGlobal && need >= 3 && c <= kArcMaxC && c > kWave) {
+        // continue from an LDS copy of this node's subgraph
+        const int W2 = copy_to_lds(H, m, c, wb.arc);
+        const HeavyCtx HL{wb.arc, W2, H.L, H.tag};
+        const int rem = c - 64 * lane;
+        const u64 all = lane < W2 ? (rem >= 64 ? ~0ull : ((1ull << rem) - 1)) : 0ull;
+        if (kStats && lane == 0) A.st[kStatArcLds] += 1;
+        if (heavy_node<kStats, kPerArc, false>(HL, all, c, need, lvl, wb, A, uacc, per_arc))
+            heavy_dfs<kStats, kPerArc, false>(HL, all, need, lvl, wb, A, uacc, per_arc);
+        __builtin_amdgcn_wave_barrier();
         return false;
     }
     if (c <= kWave) {
@@ -381,9 +483,9 @@ __device__ __forceinline__ bool heavy_node(const HeavyCtx& H, u64 m, int c, int 
 }
 
 // Depth-first search, all lanes in step, below a node with mask M (more
-// than 64 candidates, `need` more vertices), rows in H.
-template <bool kStats, bool kPerArc>
-__device__ __forceinline__ void heavy_dfs(const HeavyCtx& H, u64 M, int need0, WaveBuf& wb, Acc& A,
+// than 64 candidates, need0 more vertices), rows in H; stack levels from lvl0.
+template <bool kStats, bool kPerArc, bool kGlobal>
+__device__ __forceinline__ void heavy_dfs(const HeavyCtx& H, u64 M, int need0, int lvl0, WaveBuf& wb, Acc& A,
                                           u64& uacc, u64* per_arc)
 {
     const int q = lane_of();
@@ -394,8 +496,8 @@ __device__ __forceinline__ void heavy_dfs(const HeavyCtx& H, u64 M, int need0, W
         if (b == 0ull) {
             if (t == 1) break;
             --t;
-            M = wb.hM[(t - 1) * kWave + q];
-            R = wb.hR[(t - 1) * kWave + q];
+            M = wb.hM[(lvl0 + t - 1) * kWave + q];
+            R = wb.hR[(lvl0 + t - 1) * kWave + q];
             continue;
         }
         const int f = __builtin_ctzll(b);
@@ -405,9 +507,9 @@ __device__ __forceinline__ void heavy_dfs(const HeavyCtx& H, u64 M, int need0, W
         const u64 ch = M & (q < H.W ? H.rows[(int64_t)x * H.W + q] : 0ull);
         const int cc = wave_sum_small(__popcll(ch));
         if (kStats && q == 0) A.st[kStatHeavySteps] += 1;
-        if (heavy_node<kStats, kPerArc>(H, ch, cc, need0 - t, wb, A, uacc, per_arc)) {
-            wb.hM[(t - 1) * kWave + q] = M;
-            wb.hR[(t - 1) * kWave + q] = R;
+        if (heavy_node<kStats, kPerArc, kGlobal>(H, ch, cc, need0 - t, lvl0 + t, wb, A, uacc, per_arc)) {
+            wb.hM[(lvl0 + t - 1) * kWave + q] = M;
+            wb.hR[(lvl0 + t - 1) * kWave + q] = R;
             M = ch;
             R = ch;
             ++t;
@@ -424,46 +526,8 @@ __device__ void heavy_arc(const HeavyCtx& H, int r, WaveBuf& wb, Acc& A, u64* pe
     const u64 M = q < H.W ? H.rows[(int64_t)r * H.W + q] : 0ull;
     const int c = wave_sum_small(__popcll(M));
     const int need = H.L - 1;
-    if (need >= 3 && c > kWave && c <= kArcMaxC) {
-        // copy the arc's subgraph to LDS, compacted to its c candidates
-        // (W2 = ceil(c/64) words per row): lane a rebuilds row a by
-        // extracting, word by word, the bits at the candidates' positions
-        const int W2 = (c + 63) >> 6;
-        for (int a0 = 0; a0 < c; a0 += kWave) {
-            const int a = a0 + q;
-            const int xa = wave_select(M, a, H.W);
-            const u64* __restrict__ src = H.rows + (int64_t)(a < c ? xa : 0) * H.W;
-            unsigned o[8] = {0u, 0u, 0u, 0u, 0u, 0u, 0u, 0u};
-            int b = 0;
-            for (int w = 0; w < H.W; ++w) {
-                u64 mw = readlane64(M, w);
-                if (mw == 0ull) continue;
-                const u64 word = a < c ? src[w] : 0ull;
-                const unsigned wlo = (unsigned)word, whi = (unsigned)(word >> 32);
-                while (mw) {
-                    const int p = __builtin_ctzll(mw);
-                    mw &= mw - 1;
-                    const unsigned bit = ((p < 32 ? wlo : whi) >> (p & 31)) & 1u;
-#pragma unroll
-                    for (int h = 0; h < 8; ++h)
-                        if ((b >> 5) == h) o[h] |= bit << (b & 31);
-                    ++b;
-                }
-            }
-            if (a < c)
-                for (int i = 0; i < W2; ++i) wb.arc[a * W2 + i] = ((u64)o[2 * i + 1] << 32) | o[2 * i];
-        }
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        const HeavyCtx HL{wb.arc, W2, H.L, H.tag};
-        const int rem = c - 64 * q;
-        const u64 all = q < W2 ? (rem >= 64 ? ~0ull : ((1ull << rem) - 1)) : 0ull;
-        if (kStats && q == 0) A.st[kStatArcLds] += 1;
-        heavy_dfs<kStats, kPerArc>(HL, all, need, wb, A, uacc, per_arc);
-        __builtin_amdgcn_wave_barrier();
-    } else if (heavy_node<kStats, kPerArc>(H, M, c, need, wb, A, uacc, per_arc)) {
-        heavy_dfs<kStats, kPerArc>(H, M, need, wb, A, uacc, per_arc);
-    }
+    if (heavy_node<kStats, kPerArc, true>(H, M, c, need, 0, wb, A, uacc, per_arc))
+        heavy_dfs<kStats, kPerArc, true>(H, M, need, 0, wb, A, uacc, per_arc);
     if (kPerArc) {
         const u64 s = wave_sum_u64(uacc);
         if (q == 0 && s) atomicAdd(per_arc + H.tag, s);
