@@ -36,7 +36,8 @@ enum StatSlot {
     kStatWaves = 18,       // waves that ran
     kStatArcLds = 19,      // heavy arcs searched from an LDS copy of their subgraph
     kStatNeed3Lanes = 20,  // children handled whole by one lane (two levels left)
-    kNumStats = 21
+    kStatDonations = 21,   // light-engine work donations taken by idle lanes
+    kNumStats = 22
 };
 
 // Schedule of one graph for the count kernel: vertices sorted by out-degree

@@ -38,6 +38,7 @@ constexpr int kLdsStackLevels = 8;      // deeper stacks (k > 12) live in device
 constexpr int kArcMaxC = 256;           // heavy arcs with |C_uv| <= this are copied to LDS
 constexpr int kArcWords = kArcMaxC * (kArcMaxC / 64);   // 8 KB per wave
 constexpr int kLaneMaxWords = 4;        // multi-word masks a lane holds in registers
+constexpr int kDonateMinIdle = 8;       // idle lanes that trigger work donation
 
 // ------------------------------------------------------------------ helpers
 
@@ -151,6 +152,7 @@ __host__ __device__ inline int wave_lds_bytes(int max_k)
 {
     int b = 8 * kWaveBufRows + 4 * kWaveBufRows + 4 * kWaveBufRows;   // rows, meta, tags
     b += 8 * kArcWords;                                               // arc subgraph copy
+    b += 32 * kWave;                                                  // donation mailbox
     if (stack_in_lds(max_k)) b += 8 * (int)wave_stack_words(max_k);
     return b;
 }
@@ -181,6 +183,7 @@ struct Acc {
 
 struct WaveBuf {
     u64* arc;        // LDS copy of one heavy arc's subgraph (multi-word rows)
+    u64* mbox;       // donation mailbox: per lane M, R, and (need, base, tag)
     u64* rows;
     int32_t* meta;   // (first row of the subgraph << 8) | need
     int32_t* tags;   // arc of the unit (per-arc output)
@@ -233,6 +236,61 @@ __device__ __forceinline__ void light_engine(const WaveBuf& wb, Acc& A, u64* __r
         if (act == 0ull) {
             if (next >= nunits) break;
             continue;
+        }
+        if (next >= nunits && __popcll(~act) >= kDonateMinIdle) {
+            // work donation: no unit is left and lanes are idle, so every busy
+            // lane offers the upper half of the remaining candidates of its
+            // shallowest level that still holds real work; idle lanes take
+            // them as new search roots (counts only depend on the subtree)
+            int lvl = 0;
+            u64 Ml = 0ull, Rl = 0ull;
+            if (active) {
+                for (int l = 1; l <= t; ++l) {
+                    const u64 r = (l == t) ? R : sR[(l - 1) * kWave + lane];
+                    const int pc = __popcll(r);
+                    if (pc >= 2 && (need + (t - l) >= 3 || pc >= 8)) {
+                        lvl = l;
+                        Rl = r;
+                        Ml = (l == t) ? M : sM[(l - 1) * kWave + lane];
+                        break;
+                    }
+                }
+            }
+            const u64 donors = __ballot(lvl > 0);
+            if (donors) {
+                const u64 idle = ~act;
+                const int np = min(__popcll(donors), __popcll(idle));
+                if (lvl > 0) {
+                    const int r = __popcll(donors & lt_mask);
+                    if (r < np) {
+                        const int recv = select64(idle, r);
+                        const int p = select64(Rl, __popcll(Rl) / 2);
+                        const u64 low = Rl & ((1ull << p) - 1);
+                        if (lvl == t) R = low;
+                        else sR[(lvl - 1) * kWave + lane] = low;
+                        u64* mb = wb.mbox + 4 * recv;
+                        mb[0] = Ml;
+                        mb[1] = Rl & ~low;
+                        mb[2] = ((u64)(unsigned)base << 32) | (unsigned)(need + (t - lvl));
+                        mb[3] = (u64)(unsigned)tag;
+                    }
+                }
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                __builtin_amdgcn_wave_barrier();
+                if (!active && __popcll(idle & lt_mask) < np) {
+                    const u64* mb = wb.mbox + 4 * lane;
+                    M = mb[0];
+                    R = mb[1];
+                    need = (int)(unsigned)mb[2];
+                    base = (int)(mb[2] >> 32);
+                    tag = (int)(unsigned)mb[3];
+                    t = 1;
+                    uacc = 0;
+                    active = true;
+                    if (kStats) A.st[kStatDonations] += 1;
+                }
+                __builtin_amdgcn_wave_barrier();
+            }
         }
         if (kStats && lane == 0) {
             A.st[kStatLightIters] += 1;
@@ -561,9 +619,10 @@ __global__ void __launch_bounds__(kMaxBlock) count_kernel(KParams P)
     wb.meta = reinterpret_cast<int32_t*>(wbase + 8 * kWaveBufRows);
     wb.tags = reinterpret_cast<int32_t*>(wbase + 12 * kWaveBufRows);
     wb.arc = reinterpret_cast<u64*>(wbase + 16 * kWaveBufRows);
+    wb.mbox = reinterpret_cast<u64*>(wbase + 16 * kWaveBufRows + 8 * kArcWords);
     u64* stacks;
     if (kLdsStack) {
-        stacks = reinterpret_cast<u64*>(wbase + 16 * kWaveBufRows + 8 * kArcWords);
+        stacks = reinterpret_cast<u64*>(wbase + 16 * kWaveBufRows + 8 * kArcWords + 32 * kWave);
     } else {
         stacks = P.scratch + (int64_t)blockIdx.x * P.scratch_words + (int64_t)wid * wave_stack_words(P.max_k);
     }
