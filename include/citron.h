@@ -159,8 +159,10 @@ citron_status citron_get_tuning(const citron_graph* g, citron_tuning* t);
  *        1 - [15] / ([18] ([17] - [16])) is the idle-wave fraction
  *   [19] heavy arcs searched from an LDS copy of their subgraph
  *   [20] children with two levels left handled whole by one lane
- *   [21] work donations taken by idle lanes of the light engine */
-#define CITRON_NSTATS 22
+ *   [21] work donations taken by idle lanes of the light engine
+ *   [22] longest busy time of one wave (ticks)
+ *   [23] longest single work item: (ticks << 32) | its index in the launch */
+#define CITRON_NSTATS 24
 citron_status citron_work_stats(citron_graph* g, int32_t k, uint64_t* stats);
 
 void citron_free(citron_graph* g);       /* NULL is a no-op */

@@ -31,7 +31,7 @@ citron_tuning default_tuning()
     t.wg_waves = 4;
     t.blocks_per_cu = 2;
     t.light_rows = 256;
-    t.flush_rows = 192;
+    t.flush_rows = 128;
     t.build_blocks_per_cu = 4;
     t.reserved = 0;
     return t;
@@ -125,6 +125,7 @@ static void free_graph_memory(citron_graph* g)
     dfree(g->d_hhist);
     dfree(g->d_hscan);
     dfree(g->d_hcur);
+    for (int k = 0; k <= CITRON_KMAX; ++k) dfree(g->d_buckets[k]);
     g->rows_valid = false;
     free_plan(g);
     if (g->h_small) (void)hipHostFree(g->h_small);
@@ -256,21 +257,61 @@ citron_status ensure_scratch(citron_graph* g, int64_t bytes)
     return CITRON_OK;
 }
 
-void count_items(const citron_graph* g, int32_t k, int32_t* n_harcs, int32_t* light_first, int32_t* n_lightv)
+// Work items of a k-clique count (k >= 4): heavy arcs with |C_uv| >= k-2 in
+// buckets of equal |C_uv|, light vertices with out-degree >= k-1 in buckets of
+// equal out-degree, merged into one table by cost key (|C_uv|, or out-degree
+// - 1 for a light vertex), largest first, so that the costliest work starts
+// first.  Arcs and vertices are split into parts (arc_parts, light_parts).
+citron_status ensure_buckets(citron_graph* g, int32_t k)
 {
+    if (g->d_buckets[k]) return CITRON_OK;
     const int32_t D = std::max(g->max_outdeg, 2);
-    const int32_t y = k - 2;   // |C_uv| needed by an arc
-    *n_harcs = (y >= 0 && y <= D) ? g->h_hscan[(size_t)(D - y)] : 0;
-    // vertices with out-degree >= x: h_vscan[D - x + 1] (x in 2..D)
-    auto at_least = [&](int32_t x) -> int32_t {
+    auto v_at_least = [&](int32_t x) -> int64_t {   // vertices with out-degree >= x
         if (x > D) return 0;
         if (x < 2) x = 2;
         return g->h_vscan[(size_t)(D - x + 1)];
     };
-    const int32_t n_heavy = at_least(kLightMaxDeg + 1);
-    const int32_t a = std::max(k - 1, 2);
-    *light_first = n_heavy;
-    *n_lightv = a > kLightMaxDeg ? 0 : at_least(a) - n_heavy;
+    const int64_t n_heavy = v_at_least(kLightMaxDeg + 1);
+    struct B { int32_t key, first, cnt, light; };
+    std::vector<B> hb, lb;
+    // heavy-arc buckets: bucket j of the arc order holds |C_uv| = D-1-j
+    for (int32_t j = 0; j < D; ++j) {
+        const int32_t c = D - 1 - j;
+        if (c < k - 2) break;
+        const int32_t cnt = g->h_hscan[(size_t)j + 1] - g->h_hscan[(size_t)j];
+        if (cnt > 0) hb.push_back({c, g->h_hscan[(size_t)j], cnt, 0});
+    }
+    // light-vertex buckets: out-degree d = 64 down to max(k-1, 2)
+    for (int32_t d = kLightMaxDeg; d >= std::max(k - 1, 2); --d) {
+        const int64_t cnt = v_at_least(d) - v_at_least(d + 1);
+        if (cnt > 0) lb.push_back({d - 1, (int32_t)(v_at_least(d + 1) - n_heavy), (int32_t)cnt, 1});
+    }
+    std::vector<int32_t> tab;
+    int64_t items = 0;
+    size_t ih = 0, il = 0;
+    while (ih < hb.size() || il < lb.size()) {
+        const bool take_h = il >= lb.size() || (ih < hb.size() && hb[ih].key >= lb[il].key);
+        const B b = take_h ? hb[ih++] : lb[il++];
+        const int32_t parts = b.light ? light_parts(b.key + 1, k) : arc_parts(b.key, k);
+        tab.push_back((int32_t)items);
+        tab.push_back(b.first);
+        tab.push_back(b.cnt);
+        tab.push_back((b.key << 1) | b.light);
+        items += (int64_t)b.cnt * parts;
+        if (items > 0x7fffffffLL) return fail(CITRON_EINVAL, "too many work items for one count");
+    }
+    const int32_t nb = (int32_t)(tab.size() / 4);
+    tab.push_back((int32_t)items);
+    tab.push_back(0);
+    tab.push_back(0);
+    tab.push_back(0);
+    citron_status st = dalloc(&g->d_buckets[k], tab.size(), &g->device_bytes, "item buckets");
+    if (st) return st;
+    hipError_t e = hipMemcpy(g->d_buckets[k], tab.data(), sizeof(int32_t) * tab.size(), hipMemcpyHostToDevice);
+    if (e != hipSuccess) return hip_fail(e, "item buckets");
+    g->n_buckets[k] = nb;
+    g->n_work[k] = (int32_t)items;
+    return CITRON_OK;
 }
 
 QueryDesc make_query(const citron_graph* g, int32_t k, unsigned long long* acc, int32_t* ovf,
@@ -290,9 +331,12 @@ QueryDesc make_query(const citron_graph* g, int32_t k, unsigned long long* acc, 
     q.per_arc = per_arc;
     q.stats = stats;
     q.k = k;
-    count_items(g, k, &q.n_harcs, &q.light_first, &q.n_lightv);
+    q.buckets = g->d_buckets[k];
+    q.n_buckets = g->n_buckets[k];
+    q.light_first = g->plan.n_heavy;
+    q.n_work = g->n_work[k];
     q.item_begin = item_begin;
-    q.n_items = q.n_harcs + q.n_lightv;
+    q.n_items = q.n_work;
     return q;
 }
 
@@ -339,6 +383,8 @@ static citron_status run_single(citron_graph* g, int32_t k, unsigned long long* 
         if (g->tri_ovf || c < seed) return fail(CITRON_EOVERFLOW, "count is >= 2^64; value is mod 2^64");
         return CITRON_OK;
     }
+    st = ensure_buckets(g, k);
+    if (st) return st;
     const citron_tuning& t = g->tuning;
     const int wg = t.wg_waves;
     const int32_t blocks = device_cus(g->device) * t.blocks_per_cu;

@@ -93,6 +93,10 @@ struct citron_graph {
     std::vector<int32_t> h_vscan;           // vertices by out-degree, scanned
     uint64_t tri = 0;
     bool tri_ovf = false;
+    // per k: the merged bucket table of the count's work items
+    int32_t* d_buckets[CITRON_KMAX + 1] = {};
+    int32_t n_buckets[CITRON_KMAX + 1] = {};
+    int32_t n_work[CITRON_KMAX + 1] = {};
     uint64_t build_stats[citron::kNumStats] = {};
 };
 
@@ -106,8 +110,7 @@ citron_status resolve_tuning(const citron_tuning* in, citron_tuning* out);
 int device_cus(int dev);
 citron_status ensure_plan(citron_graph* g, const citron_tuning& t);
 citron_status ensure_rows(citron_graph* g);
-// items of a k >= 4 count: heavy arcs with |C_uv| >= k-2, light vertices with out-degree >= k-1
-void count_items(const citron_graph* g, int32_t k, int32_t* n_harcs, int32_t* light_first, int32_t* n_lightv);
+citron_status ensure_buckets(citron_graph* g, int32_t k);
 citron_status check_count_args(const citron_graph* g, int32_t k, bool* trivial, uint64_t* value);
 QueryDesc make_query(const citron_graph* g, int32_t k, unsigned long long* acc, int32_t* ovf,
                      unsigned long long* per_arc, unsigned long long* stats, int32_t item_begin);

@@ -208,6 +208,13 @@ extern "C" citron_status citron_count_batch(citron_graph* const* gs, const int32
             st = ensure_rows(g);
             if (st) return st;
         }
+        for (size_t j = 0; j < key.ks.size(); ++j) {
+            citron_graph* g = const_cast<citron_graph*>(key.graphs[j]);
+            if (key.ks[j] < 4) continue;
+            std::lock_guard<std::mutex> gl(g->mu);
+            st = ensure_buckets(g, key.ks[j]);
+            if (st) return st;
+        }
         // k = 3 is the build's triangle count; the rest go to the kernel
         BatchKey kkey;
         std::vector<int32_t> kmap;

@@ -37,7 +37,9 @@ enum StatSlot {
     kStatArcLds = 19,      // heavy arcs searched from an LDS copy of their subgraph
     kStatNeed3Lanes = 20,  // children handled whole by one lane (two levels left)
     kStatDonations = 21,   // light-engine work donations taken by idle lanes
-    kNumStats = 22
+    kStatWaveBusyMax = 22, // longest busy time of one wave (atomic max)
+    kStatItemMax = 23,     // longest item: (ticks << 32) | item index (atomic max)
+    kNumStats = 24
 };
 
 // Schedule of one graph for the count kernel: vertices sorted by out-degree
@@ -75,14 +77,40 @@ struct QueryDesc {
     int32_t* overflow;           // set to 1 when an addition carried
     unsigned long long* per_arc; // optional per-arc counts (nullptr: off)
     unsigned long long* stats;   // optional work counters (nullptr: off)
-    int32_t k;
-    int32_t n_harcs;             // heavy arcs with |C_uv| >= k - 2 (a prefix of harcs)
+    // Work items, in buckets of equal cost key, largest key first: heavy-arc
+    // buckets (key |C_uv|) and light-vertex buckets (key out-degree - 1),
+    // merged.  Bucket b: buckets[4b] = first item, [4b+1] = first arc (index
+    // into harcs) or first light vertex (index into the light part of order),
+    // [4b+2] = arcs or vertices in the bucket, [4b+3] = key << 1 | light.
+    // An arc or vertex is split into parts (arc_parts / light_parts); items
+    // of a bucket are part-major.  buckets[4 n_buckets] = item count.
+    const int32_t* buckets;
+    int32_t n_buckets;
     int32_t light_first;         // index in order of the first light vertex
-    int32_t n_lightv;            // light vertices with out-degree >= k - 1
+    int32_t k;
+    int32_t n_work;              // items of the query (all buckets)
     int32_t item_begin;          // first global item of this query
     int32_t n_items;             // items of this query in the launch
     int32_t item_lo;             // local index of the query's first item in the launch
     int32_t pad;
 };
+
+// Parts a heavy arc with |C_uv| = c is split into for a k-clique count; each
+// part takes every P-th first-level branch of the arc (speed only).
+__host__ __device__ inline int arc_parts(int c, int k)
+{
+    if (k <= 5) return 1;
+    if (k == 6) return c < 64 ? 1 : (c / 32 < 8 ? c / 32 : 8);
+    return c < 16 ? 1 : (c / 8 < 32 ? c / 8 : 32);
+}
+
+// Parts a light vertex (out-degree d <= 64, its subgraph one word per row)
+// is split into; each part takes every P-th arc of the vertex (speed only).
+__host__ __device__ inline int light_parts(int d, int k)
+{
+    if (k <= 5) return 1;
+    if (k == 6) return d >= 32 ? d / 8 : 1;
+    return d >= 12 ? d / 2 : 1;
+}
 
 }  // namespace citron

@@ -98,7 +98,7 @@ __device__ void wave_flush(u64 acc, int ovf, u64* dst, int32_t* ovf_dst)
 __device__ void wave_flush_stats(const u64* vals, u64* dst)
 {
     for (int i = 0; i < kNumStats; ++i) {
-        if (i >= kStatWaveBusy && i <= kStatWaves) continue;   // written once per wave at exit
+        if ((i >= kStatWaveBusy && i <= kStatWaves) || i >= kStatWaveBusyMax) continue;   // written once per wave
         const u64 v = wave_sum_u64(vals[i]);
         if (lane_of() == 0 && v) atomicAdd(dst + i, v);
     }
@@ -153,6 +153,7 @@ __host__ __device__ inline int wave_lds_bytes(int max_k)
     int b = 8 * kWaveBufRows + 4 * kWaveBufRows + 4 * kWaveBufRows;   // rows, meta, tags
     b += 8 * kArcWords;                                               // arc subgraph copy
     b += 32 * kWave;                                                  // donation mailbox
+    b += 4 * kWaveBufRows;                                            // unit list
     if (stack_in_lds(max_k)) b += 8 * (int)wave_stack_words(max_k);
     return b;
 }
@@ -191,7 +192,9 @@ struct WaveBuf {
     u64* sR;
     u64* hM;         // heavy stacks
     u64* hR;
+    int32_t* units;  // rows that are search roots (a part of a split arc uses some rows only)
     int n;           // rows in use (wave-uniform)
+    int nu;          // units in use (wave-uniform)
 };
 
 template <bool kStats, bool kPerArc>
@@ -202,7 +205,7 @@ __device__ __forceinline__ void light_engine(const WaveBuf& wb, Acc& A, u64* __r
     const u64* __restrict__ rows = wb.rows;
     u64* __restrict__ sM = wb.sM;
     u64* __restrict__ sR = wb.sR;
-    const int nunits = wb.n;
+    const int nunits = wb.nu;
     int next = 0;                      // wave-uniform unit counter
     bool active = false;
     u64 M = 0, R = 0, uacc = 0;
@@ -213,13 +216,14 @@ __device__ __forceinline__ void light_engine(const WaveBuf& wb, Acc& A, u64* __r
             const int u = next + __popcll(want & lt_mask);
             next += __popcll(want);
             if (!active && u < nunits) {
-                const int mt = wb.meta[u];
-                const u64 m1 = rows[u];
+                const int row = wb.units[u];
+                const int mt = wb.meta[row];
+                const u64 m1 = rows[row];
                 base = mt >> 8;
                 need = mt & 255;
                 const int c = __popcll(m1);
                 if (kStats) A.st[kStatLightUnits] += 1;
-                if (kPerArc) tag = wb.tags[u];
+                if (kPerArc) tag = wb.tags[row];
                 if (need == 1) {
                     A.acc += (u64)c;
                     if (kPerArc && c) atomicAdd(per_arc + tag, (u64)c);
@@ -356,6 +360,7 @@ __device__ __forceinline__ void flush_tasks(WaveBuf& wb, Acc& A, u64* per_arc)
     light_engine<kStats, kPerArc>(wb, A, per_arc);
     __builtin_amdgcn_wave_barrier();
     wb.n = 0;
+    wb.nu = 0;
 }
 
 // ------------------------------------------------------------ heavy engine
@@ -371,8 +376,8 @@ struct HeavyCtx {
 // Returns true when the caller must search it depth first (c > 64 and
 // need >= 3).
 template <bool kStats, bool kPerArc, bool kGlobal>
-__device__ __forceinline__ void heavy_dfs(const HeavyCtx& H, u64 M, int need0, int lvl0, WaveBuf& wb, Acc& A,
-                                          u64& uacc, u64* per_arc);
+__device__ __forceinline__ void heavy_dfs(const HeavyCtx& H, u64 M, int need0, int lvl0, int part, int P,
+                                          WaveBuf& wb, Acc& A, u64& uacc, u64* per_arc);
 
 // Copy the subgraph induced on the c candidates of m (rows in H, device
 // memory) to the wave's LDS buffer, compacted to W2 = ceil(c/64) words per
@@ -414,10 +419,11 @@ __device__ __forceinline__ int copy_to_lds(const HeavyCtx& H, u64 M, int c, u64*
 // Handle a node with mask m (c candidates, `need` more vertices to choose;
 // rows in device memory when kGlobal, else in the wave's LDS copy).  Returns
 // true when the caller must search it depth first.  lvl is the first free
-// level of the heavy stacks.
+// level of the heavy stacks.  Only first-level branches j = part (mod P)
+// of the node are taken (P > 1 at the root of a split arc only).
 template <bool kStats, bool kPerArc, bool kGlobal>
-__device__ __forceinline__ bool heavy_node(const HeavyCtx& H, u64 m, int c, int need, int lvl, WaveBuf& wb,
-                                           Acc& A, u64& uacc, u64* per_arc)
+__device__ __forceinline__ bool heavy_node(const HeavyCtx& H, u64 m, int c, int need, int lvl, int part, int P,
+                                           WaveBuf& wb, Acc& A, u64& uacc, u64* per_arc)
 {
     const int lane = lane_of();
     if (c < need) return false;
@@ -451,8 +457,10 @@ __device__ __forceinline__ bool heavy_node(const HeavyCtx& H, u64 m, int c, int 
         // two levels left, many candidates: lane j takes the j-th candidate
         // x, forms its child mask m AND row_x (at most 4 words, in
         // registers) and sums the last level of that child itself
-        for (int j0 = 0; j0 < c; j0 += kWave) {
-            const int j = j0 + lane;
+        const int nj = (c - part + P - 1) / P;
+        for (int j0 = 0; j0 < nj; j0 += kWave) {
+            const int jj = j0 + lane;
+            const int j = jj < nj ? part + P * jj : c;
             const int x = wave_select(m, j, H.W);
             u64 ch[kLaneMaxWords];
             const u64* __restrict__ rx = H.rows + (int64_t)(j < c ? x : 0) * H.W;
@@ -498,8 +506,8 @@ __device__ __forceinline__ bool heavy_node(const HeavyCtx& H, u64 m, int c, int 
         const int rem = c - 64 * lane;
         const u64 all = lane < W2 ? (rem >= 64 ? ~0ull : ((1ull << rem) - 1)) : 0ull;
         if (kStats && lane == 0) A.st[kStatArcLds] += 1;
-        if (heavy_node<kStats, kPerArc, false>(HL, all, c, need, lvl, wb, A, uacc, per_arc))
-            heavy_dfs<kStats, kPerArc, false>(HL, all, need, lvl, wb, A, uacc, per_arc);
+        if (heavy_node<kStats, kPerArc, false>(HL, all, c, need, lvl, part, P, wb, A, uacc, per_arc))
+            heavy_dfs<kStats, kPerArc, false>(HL, all, need, lvl, part, P, wb, A, uacc, per_arc);
         __builtin_amdgcn_wave_barrier();
         return false;
     }
@@ -530,6 +538,10 @@ __device__ __forceinline__ bool heavy_node(const HeavyCtx& H, u64 m, int c, int 
             wb.meta[wb.n + lane] = (wb.n << 8) | (need - 1);
             if (kPerArc) wb.tags[wb.n + lane] = H.tag;
         }
+        const bool unit = lane < c && (P == 1 || lane % P == part);
+        const u64 um = __ballot(unit);
+        if (unit) wb.units[wb.nu + __popcll(um & (lane == 0 ? 0ull : (~0ull >> (kWave - lane))))] = wb.n + lane;
+        wb.nu += __popcll(um);
         wb.n += c;
         if (kStats && lane == 0) {
             A.st[kStatCompactions] += 1;
@@ -543,12 +555,13 @@ __device__ __forceinline__ bool heavy_node(const HeavyCtx& H, u64 m, int c, int 
 // Depth-first search, all lanes in step, below a node with mask M (more
 // than 64 candidates, need0 more vertices), rows in H; stack levels from lvl0.
 template <bool kStats, bool kPerArc, bool kGlobal>
-__device__ __forceinline__ void heavy_dfs(const HeavyCtx& H, u64 M, int need0, int lvl0, WaveBuf& wb, Acc& A,
-                                          u64& uacc, u64* per_arc)
+__device__ __forceinline__ void heavy_dfs(const HeavyCtx& H, u64 M, int need0, int lvl0, int part, int P,
+                                          WaveBuf& wb, Acc& A, u64& uacc, u64* per_arc)
 {
     const int q = lane_of();
     u64 R = M;
     int t = 1;
+    int jroot = 0;
     for (;;) {
         const u64 b = __ballot(R != 0ull);
         if (b == 0ull) {
@@ -562,10 +575,14 @@ __device__ __forceinline__ void heavy_dfs(const HeavyCtx& H, u64 M, int need0, i
         const u64 Rf = readlane64(R, f);
         const int x = f * 64 + __builtin_ctzll(Rf);
         if (q == f) R &= R - 1;
+        if (t == 1) {
+            const int jr = jroot++;
+            if (P > 1 && jr % P != part) continue;
+        }
         const u64 ch = M & (q < H.W ? H.rows[(int64_t)x * H.W + q] : 0ull);
         const int cc = wave_sum_small(__popcll(ch));
         if (kStats && q == 0) A.st[kStatHeavySteps] += 1;
-        if (heavy_node<kStats, kPerArc, kGlobal>(H, ch, cc, need0 - t, lvl0 + t, wb, A, uacc, per_arc)) {
+        if (heavy_node<kStats, kPerArc, kGlobal>(H, ch, cc, need0 - t, lvl0 + t, 0, 1, wb, A, uacc, per_arc)) {
             wb.hM[(lvl0 + t - 1) * kWave + q] = M;
             wb.hR[(lvl0 + t - 1) * kWave + q] = R;
             M = ch;
@@ -577,15 +594,15 @@ __device__ __forceinline__ void heavy_dfs(const HeavyCtx& H, u64 M, int need0, i
 }
 
 template <bool kStats, bool kPerArc>
-__device__ void heavy_arc(const HeavyCtx& H, int r, WaveBuf& wb, Acc& A, u64* per_arc)
+__device__ void heavy_arc(const HeavyCtx& H, int r, int part, int P, WaveBuf& wb, Acc& A, u64* per_arc)
 {
     const int q = lane_of();
     u64 uacc = 0;
     const u64 M = q < H.W ? H.rows[(int64_t)r * H.W + q] : 0ull;
     const int c = wave_sum_small(__popcll(M));
     const int need = H.L - 1;
-    if (heavy_node<kStats, kPerArc, true>(H, M, c, need, 0, wb, A, uacc, per_arc))
-        heavy_dfs<kStats, kPerArc, true>(H, M, need, 0, wb, A, uacc, per_arc);
+    if (heavy_node<kStats, kPerArc, true>(H, M, c, need, 0, part, P, wb, A, uacc, per_arc))
+        heavy_dfs<kStats, kPerArc, true>(H, M, need, 0, part, P, wb, A, uacc, per_arc);
     if (kPerArc) {
         const u64 s = wave_sum_u64(uacc);
         if (q == 0 && s) atomicAdd(per_arc + H.tag, s);
@@ -620,9 +637,10 @@ __global__ void __launch_bounds__(kMaxBlock) count_kernel(KParams P)
     wb.tags = reinterpret_cast<int32_t*>(wbase + 12 * kWaveBufRows);
     wb.arc = reinterpret_cast<u64*>(wbase + 16 * kWaveBufRows);
     wb.mbox = reinterpret_cast<u64*>(wbase + 16 * kWaveBufRows + 8 * kArcWords);
+    wb.units = reinterpret_cast<int32_t*>(wbase + 16 * kWaveBufRows + 8 * kArcWords + 32 * kWave);
     u64* stacks;
     if (kLdsStack) {
-        stacks = reinterpret_cast<u64*>(wbase + 16 * kWaveBufRows + 8 * kArcWords + 32 * kWave);
+        stacks = reinterpret_cast<u64*>(wbase + 20 * kWaveBufRows + 8 * kArcWords + 32 * kWave);
     } else {
         stacks = P.scratch + (int64_t)blockIdx.x * P.scratch_words + (int64_t)wid * wave_stack_words(P.max_k);
     }
@@ -632,6 +650,7 @@ __global__ void __launch_bounds__(kMaxBlock) count_kernel(KParams P)
     wb.hM = stacks + 2ll * levels * kWave;
     wb.hR = stacks + 3ll * levels * kWave;
     wb.n = 0;
+    wb.nu = 0;
 
     Acc A;
     A.acc = 0ull;
@@ -640,6 +659,7 @@ __global__ void __launch_bounds__(kMaxBlock) count_kernel(KParams P)
     int cur = -1;                      // query whose work the wave holds
     u64* per_arc = nullptr;
     const u64 t_start = kStats ? wall_clock64() : 0ull;
+    u64 item_max = 0ull;
 
     for (;;) {
         int g = 0;
@@ -672,15 +692,31 @@ __global__ void __launch_bounds__(kMaxBlock) count_kernel(KParams P)
         }
         const int i = q.item_lo + (g - q.item_begin);
         const int k = q.k;
-        if (i < q.n_harcs) {
-            const int e = q.rows.harcs[i];
+        const u64 t_item = kStats ? wall_clock64() : 0ull;
+        // bucket holding item i, then the arc or vertex and the part (part-major)
+        int lo = 0, hi = q.n_buckets - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (q.buckets[4 * mid] <= i) lo = mid;
+            else hi = mid - 1;
+        }
+        const int key = q.buckets[4 * lo + 3] >> 1;
+        const bool light = (q.buckets[4 * lo + 3] & 1) != 0;
+        const int cnt = q.buckets[4 * lo + 2];
+        const int local = i - q.buckets[4 * lo];
+        const int part = local / cnt;
+        const int which = q.buckets[4 * lo + 1] + (local - part * cnt);
+        if (!light) {
+            const int P = arc_parts(key, k);
+            const int e = q.rows.harcs[which];
             const int u = q.dag_src[e];
             const int a0 = q.dag_ptr[u];
             const int d = q.dag_ptr[u + 1] - a0;
             HeavyCtx H{q.rows.rows + q.rows.rows_off[u], (d + 63) >> 6, k - 1, e};
-            heavy_arc<kStats, kPerArc>(H, e - a0, wb, A, per_arc);
+            heavy_arc<kStats, kPerArc>(H, e - a0, part, P, wb, A, per_arc);
         } else {
-            const int u = q.order[q.light_first + (i - q.n_harcs)];
+            const int P = light_parts(key + 1, k);
+            const int u = q.order[q.light_first + which];
             const int a0 = q.dag_ptr[u];
             const int d = q.dag_ptr[u + 1] - a0;
             if (wb.n + d > kWaveBufRows) flush_tasks<kStats, kPerArc>(wb, A, per_arc);
@@ -689,9 +725,17 @@ __global__ void __launch_bounds__(kMaxBlock) count_kernel(KParams P)
                 wb.meta[wb.n + lane] = (wb.n << 8) | (k - 2);
                 if (kPerArc) wb.tags[wb.n + lane] = a0 + lane;
             }
+            const bool unit = lane < d && (P == 1 || lane % P == part);
+            const u64 um = __ballot(unit);
+            if (unit) wb.units[wb.nu + __popcll(um & (lane == 0 ? 0ull : (~0ull >> (kWave - lane))))] = wb.n + lane;
+            wb.nu += __popcll(um);
             wb.n += d;
         }
         if (wb.n >= P.flush_rows) flush_tasks<kStats, kPerArc>(wb, A, per_arc);
+        if (kStats && lane == 0) {
+            const u64 dt = wall_clock64() - t_item;
+            if (dt > (item_max >> 32)) item_max = (dt << 32) | (u64)(unsigned)g;
+        }
     }
     if (cur >= 0) {
         const QueryDesc& oq = P.queries[cur];
@@ -707,6 +751,8 @@ __global__ void __launch_bounds__(kMaxBlock) count_kernel(KParams P)
         atomicMin(st + kStatWaveFirst, t_start);
         atomicMax(st + kStatWaveLast, t_end);
         atomicAdd(st + kStatWaves, 1ull);
+        atomicMax(st + kStatWaveBusyMax, t_end - t_start);
+        atomicMax(st + kStatItemMax, item_max);
     }
 }
 

@@ -152,6 +152,16 @@ void worker_main(citron_server* s)
                     continue;
                 }
                 if (s->free_slots.empty() || s->used + r.footprint > s->budget) break;
+                {
+                    std::lock_guard<std::mutex> gl(g->mu);
+                    st = ensure_buckets(g, r.k);
+                }
+                if (st) {
+                    r.t_admit = now_ns();
+                    complete(s, r, 0, st);
+                    s->pending.pop_front();
+                    continue;
+                }
                 r.slot = s->free_slots.back();
                 s->free_slots.pop_back();
                 s->used += r.footprint;
