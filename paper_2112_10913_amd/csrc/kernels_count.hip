@@ -39,6 +39,8 @@ constexpr int kArcMaxC = 256;           // heavy arcs with |C_uv| <= this are co
 constexpr int kArcWords = kArcMaxC * (kArcMaxC / 64);   // 8 KB per wave
 constexpr int kLaneMaxWords = 4;        // multi-word masks a lane holds in registers
 constexpr int kDonateMinIdle = 8;       // idle lanes that trigger work donation
+constexpr int kBurstIters = 32;         // last-level steps of one leaf burst at most
+constexpr int kBurstMinLanes = 32;      // lanes at a last-level node to keep a burst going
 
 // ------------------------------------------------------------------ helpers
 
@@ -331,6 +333,31 @@ __device__ __forceinline__ void light_engine(const WaveBuf& wb, Acc& A, u64* __r
                         ++t;
                         --need;
                         if (kStats) A.st[kStatPushes] += 1;
+                    }
+                }
+            }
+            if (need == 2 && R != 0ull) {
+                // leaf burst: while most lanes sit at a last-level node, run
+                // only last-level steps, two candidates at a time
+                for (int it = 0; it < kBurstIters; ++it) {
+                    const bool leaf = R != 0ull;
+                    if (__popcll(__ballot(leaf)) < kBurstMinLanes) break;
+                    if (leaf) {
+                        const int x1 = __builtin_ctzll(R);
+                        R &= R - 1;
+                        const u64 r1 = rows[base + x1];
+                        u64 r2 = 0ull;
+                        int two = 0;
+                        if (R != 0ull) {
+                            const int x2 = __builtin_ctzll(R);
+                            R &= R - 1;
+                            r2 = rows[base + x2];
+                            two = 1;
+                        }
+                        const u64 c = (u64)(__popcll(M & r1) + __popcll(M & r2));
+                        A.acc += c;
+                        if (kPerArc) uacc += c;
+                        if (kStats) A.st[kStatWordOps] += 1 + two;
                     }
                 }
             }
