@@ -115,6 +115,20 @@ uint64_t citron_count(citron_graph* g, int32_t k, citron_status* st);
 uint64_t citron_count_per_arc(citron_graph* g, int32_t k, uint64_t* per_arc,
                               citron_status* st);
 
+/* Edge-rooted counts of selected arcs (Section III-B: the k-cliques rooted
+ * at an edge are the (k-2)-cliques of the subgraph induced by the common
+ * out-neighbours of its endpoints): out[i] = the number of k-cliques whose
+ * two lowest vertices in the degree ordering are the endpoints of DAG arc
+ * arcs[i], 2 <= k <= CITRON_KMAX.  arcs (int32[n], arc indices in
+ * citron_get_dag order, each in 0..m-1, repeats allowed) and out (uint64[n])
+ * are device pointers owned by the caller; 0 <= n <= 2^26.  The count kernel
+ * runs in its usual launch configuration over the listed arcs only, heavy
+ * ones split into parts as in a full count.  Returns the sum of out
+ * (mod 2^64); *st = CITRON_EINVAL for an index outside 0..m-1 (checked on
+ * the device before any count), CITRON_EOVERFLOW if the sum wrapped. */
+uint64_t citron_count_arcs(citron_graph* g, int32_t k, const int32_t* arcs, int32_t n,
+                           uint64_t* out, citron_status* st);
+
 /* Many (graph, k) queries in one persistent launch, replayed from a
  * captured HIP graph when the same query set is submitted again.  All
  * graphs must be ORDERED and share one device.  counts and sts are host

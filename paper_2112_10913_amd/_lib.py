@@ -96,6 +96,8 @@ def load_library():
     lib.citron_count.restype = ctypes.c_uint64
     lib.citron_count_per_arc.argtypes = [vp, ctypes.c_int32, vp, _i32p]
     lib.citron_count_per_arc.restype = ctypes.c_uint64
+    lib.citron_count_arcs.argtypes = [vp, ctypes.c_int32, vp, ctypes.c_int32, vp, _i32p]
+    lib.citron_count_arcs.restype = ctypes.c_uint64
     lib.citron_count_batch.argtypes = [ctypes.POINTER(vp), _i32p, ctypes.c_int32, _u64p, _i32p,
                                        ctypes.POINTER(_Tuning)]
     lib.citron_count_batch.restype = ctypes.c_int32
@@ -249,6 +251,19 @@ class Graph:
             raise _err(st.value)
         arr = buf[:self.m].cpu().numpy().view(np.uint64)
         return int(v), arr
+
+    def count_arcs(self, k: int, arcs) -> np.ndarray:
+        """Edge-rooted k-clique counts of the listed DAG arcs (uint64 array)."""
+        torch = _torch()
+        a = torch.as_tensor(np.ascontiguousarray(arcs, dtype=np.int32)).cuda()
+        n = int(a.numel())
+        out = torch.zeros(max(n, 1), dtype=torch.int64, device="cuda")
+        st = ctypes.c_int32(0)
+        load_library().citron_count_arcs(self._handle(), int(k), a.data_ptr(), n, out.data_ptr(),
+                                         ctypes.byref(st))
+        if st.value not in (OK, EOVERFLOW):
+            raise _err(st.value)
+        return out[:n].cpu().numpy().view(np.uint64)
 
     def dag(self) -> tuple[np.ndarray, np.ndarray]:
         dptr = np.zeros(self.n + 1, np.int32)

@@ -358,9 +358,42 @@ citron_status check_count_args(const citron_graph* g, int32_t k, bool* trivial, 
     return CITRON_OK;
 }
 
+// (slot, part) items of an arc list, in device buffers freed with the object.
+struct ListItems {
+    int32_t* parts = nullptr;
+    int32_t* offs = nullptr;
+    int32_t* ws = nullptr;
+    int32_t* items = nullptr;
+    int32_t total = 0;
+    ~ListItems()
+    {
+        for (int32_t* p : {parts, offs, ws, items})
+            if (p) (void)hipFree(p);
+    }
+    citron_status build(const citron_graph* g, const int32_t* arcs, int32_t n, int32_t k, hipStream_t s)
+    {
+        if (hipMalloc((void**)&parts, sizeof(int32_t) * (size_t)n) != hipSuccess ||
+            hipMalloc((void**)&offs, sizeof(int32_t) * ((size_t)n + 1)) != hipSuccess ||
+            hipMalloc((void**)&ws, sizeof(int32_t) * scan_workspace_ints(n)) != hipSuccess)
+            return fail(CITRON_ENOMEM, "hipMalloc failed for the arc list");
+        hipError_t e = launch_list_parts(arcs, n, g->d_dag_src, g->d_dag_ptr, g->d_arc_c, k, parts, s);
+        if (e == hipSuccess) e = scan_exclusive(parts, offs, n, ws, s);
+        if (e == hipSuccess) e = hipMemcpyAsync(&g->h_small->ends[0], offs + n, sizeof(int32_t),
+                                                hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        if (e != hipSuccess) return hip_fail(e, "arc list parts");
+        total = g->h_small->ends[0];
+        if (hipMalloc((void**)&items, sizeof(int32_t) * 2 * ((size_t)total + 1)) != hipSuccess)
+            return fail(CITRON_ENOMEM, "hipMalloc failed for the arc list");
+        e = launch_list_items(n, parts, offs, items, s);
+        if (e != hipSuccess) return hip_fail(e, "arc list items");
+        return CITRON_OK;
+    }
+};
+
 // One query through the count kernel; synchronous on the graph's stream.
 static citron_status run_single(citron_graph* g, int32_t k, unsigned long long* per_arc, bool stats,
-                                uint64_t* out_count)
+                                uint64_t* out_count, const int32_t* arc_list = nullptr, int32_t n_list = 0)
 {
     std::lock_guard<std::mutex> lock(g->mu);
     hipError_t e = hipSetDevice(g->device);
@@ -371,6 +404,13 @@ static citron_status run_single(citron_graph* g, int32_t k, unsigned long long* 
     g->seed_pending = false;
     hipStream_t s = g->stream;
     if (stats) memset(g->h_small->stats, 0, sizeof(g->h_small->stats));
+    if (k == 3 && arc_list) {
+        e = launch_gather_arc_c(arc_list, n_list, g->d_arc_c, per_arc, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        if (e != hipSuccess) return hip_fail(e, "per-arc copy");
+        *out_count = 0;   // the caller sums the listed arcs
+        return CITRON_OK;
+    }
     if (k == 3) {
         // triangles: the popcounts of the rows, summed by the build
         if (per_arc) {
@@ -403,8 +443,18 @@ static citron_status run_single(citron_graph* g, int32_t k, unsigned long long* 
     if (stats && ((e = launch_fill_u64(g->d_stats, 0, kNumStats, s)) != hipSuccess ||
                   (e = launch_fill_u64(g->d_stats + kStatWaveFirst, ~0ull, 1, s)) != hipSuccess))
         return hip_fail(e, "fill");
-    if (per_arc && (e = launch_fill_u64(per_arc, 0, g->m, s)) != hipSuccess) return hip_fail(e, "fill");
+    if (per_arc && (e = launch_fill_u64(per_arc, 0, arc_list ? n_list : g->m, s)) != hipSuccess)
+        return hip_fail(e, "fill");
     g->h_small->query = make_query(g, k, &sd->acc, &sd->overflow, per_arc, stats ? g->d_stats : nullptr, 0);
+    ListItems li;
+    if (arc_list) {
+        // items of the listed arcs: heavy ones split into parts like the full schedule
+        st = li.build(g, arc_list, n_list, k, s);
+        if (st) return st;
+        g->h_small->query.arc_list = arc_list;
+        g->h_small->query.arc_items = li.items;
+        g->h_small->query.n_items = li.total;
+    }
     if (!g->d_query) {
         st = dalloc(&g->d_query, 1, &g->device_bytes, "query");
         if (st) return st;
@@ -595,6 +645,53 @@ uint64_t citron_count_per_arc(citron_graph* g, int32_t k, uint64_t* per_arc, cit
     uint64_t c = 0;
     *st = run_single(g, k, (unsigned long long*)per_arc, false, &c);
     if (*st && *st != CITRON_EOVERFLOW) return 0;
+    return c;
+}
+
+uint64_t citron_count_arcs(citron_graph* g, int32_t k, const int32_t* arcs, int32_t n, uint64_t* out,
+                           citron_status* st_out)
+{
+    citron_status dummy;
+    citron_status* st = st_out ? st_out : &dummy;
+    if (k < 2) { *st = fail(CITRON_EINVAL, "per-arc counts need k >= 2"); return 0; }
+    if (n < 0 || n > (1 << 26) || (n > 0 && (!arcs || !out))) {
+        *st = fail(CITRON_EINVAL, "arc list: NULL pointer or n outside 0..2^26");
+        return 0;
+    }
+    bool trivial;
+    uint64_t v;
+    *st = check_count_args(g, k, &trivial, &v);
+    if (*st) return 0;
+    if (n == 0) return 0;
+    {
+        std::lock_guard<std::mutex> lock(g->mu);
+        hipError_t e = hipSetDevice(g->device);
+        int32_t* err = &g->d_small->err;
+        if (e == hipSuccess) e = launch_fill_i32(err, 0, 1, g->stream);
+        if (e == hipSuccess) e = launch_check_arcs(arcs, n, g->m, err, g->stream);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(&g->h_small->err, err, sizeof(int32_t), hipMemcpyDeviceToHost, g->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(g->stream);
+        if (e != hipSuccess) { *st = hip_fail(e, "arc list check"); return 0; }
+        if (g->h_small->err) { *st = fail(CITRON_EINVAL, "arc index out of range"); return 0; }
+        if (trivial) {
+            e = launch_fill_u64((unsigned long long*)out, k == 2 ? 1ull : 0ull, n, g->stream);
+            if (e == hipSuccess) e = hipStreamSynchronize(g->stream);
+            if (e != hipSuccess) { *st = hip_fail(e, "fill"); return 0; }
+            return k == 2 ? (uint64_t)n : 0;
+        }
+    }
+    uint64_t c = 0;
+    *st = run_single(g, k, (unsigned long long*)out, false, &c, arcs, n);
+    if (*st && *st != CITRON_EOVERFLOW) return 0;
+    if (k == 3) {   // sum of the gathered sizes
+        std::vector<uint64_t> h((size_t)n);
+        if (hipMemcpy(h.data(), out, sizeof(uint64_t) * (size_t)n, hipMemcpyDeviceToHost) != hipSuccess) {
+            *st = fail(CITRON_EDEVICE, "copy");
+            return 0;
+        }
+        for (uint64_t x : h) c += x;
+    }
     return c;
 }
 

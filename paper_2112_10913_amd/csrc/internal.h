@@ -93,6 +93,11 @@ struct QueryDesc {
     int32_t n_items;             // items of this query in the launch
     int32_t item_lo;             // local index of the query's first item in the launch
     int32_t pad;
+    // list mode (arc_list != nullptr): item j is (slot, part) = (arc_items[2j],
+    // arc_items[2j+1] & 0xffff) of arc arc_list[slot], split into
+    // arc_items[2j+1] >> 16 parts; its counts go to per-arc slot `slot`
+    const int32_t* arc_list;
+    const int32_t* arc_items;
 };
 
 // Parts a heavy arc with |C_uv| = c is split into for a k-clique count; each

@@ -720,6 +720,31 @@ __global__ void __launch_bounds__(kMaxBlock) count_kernel(KParams P)
         const int i = q.item_lo + (g - q.item_begin);
         const int k = q.k;
         const u64 t_item = kStats ? wall_clock64() : 0ull;
+        if (q.arc_list) {
+            // list mode: one part of one listed arc; counts go to its list slot
+            const int slot = q.arc_items[2 * i];
+            const int pw = q.arc_items[2 * i + 1];
+            const int e = q.arc_list[slot];
+            const int u = q.dag_src[e];
+            const int a0 = q.dag_ptr[u];
+            const int d = q.dag_ptr[u + 1] - a0;
+            if (d > kLightMaxDeg) {
+                HeavyCtx H{q.rows.rows + q.rows.rows_off[u], (d + 63) >> 6, k - 1, slot};
+                heavy_arc<kStats, kPerArc>(H, e - a0, pw & 0xffff, pw >> 16, wb, A, per_arc);
+            } else {
+                if (wb.n + d > kWaveBufRows) flush_tasks<kStats, kPerArc>(wb, A, per_arc);
+                if (lane < d) {
+                    wb.rows[wb.n + lane] = q.rows.rows[q.rows.rows_off[u] + lane];
+                    wb.meta[wb.n + lane] = (wb.n << 8) | (k - 2);
+                    if (kPerArc) wb.tags[wb.n + lane] = slot;
+                }
+                if (lane == 0) wb.units[wb.nu] = wb.n + (e - a0);
+                wb.nu += 1;
+                wb.n += d;
+            }
+            if (wb.n >= P.flush_rows) flush_tasks<kStats, kPerArc>(wb, A, per_arc);
+            continue;
+        }
         // bucket holding item i, then the arc or vertex and the part (part-major)
         int lo = 0, hi = q.n_buckets - 1;
         while (lo < hi) {
@@ -897,6 +922,74 @@ __global__ void plan_header_kernel(const int32_t* __restrict__ hist_scan, int32_
     h->n_items = n_split * h->split_factor + (n_heavy - n_split) + n_batches;
     h->light_rows = light_rows;
     h->max_rows = light_rows + kLightMaxDeg - 1;
+}
+
+__global__ void check_arcs_kernel(const int32_t* __restrict__ arcs, int32_t n, int64_t m, int32_t* __restrict__ err)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n && (arcs[i] < 0 || (int64_t)arcs[i] >= m)) atomicOr(err, 1);
+}
+
+__global__ void gather_arc_c_kernel(const int32_t* __restrict__ arcs, int32_t n, const int32_t* __restrict__ arc_c,
+                                    u64* __restrict__ out)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) out[i] = (u64)arc_c[arcs[i]];
+}
+
+// parts of each listed arc (heavy sources split as in the full schedule)
+__global__ void list_parts_kernel(const int32_t* __restrict__ arcs, int32_t n, const int32_t* __restrict__ dag_src,
+                                  const int32_t* __restrict__ dag_ptr, const int32_t* __restrict__ arc_c, int32_t k,
+                                  int32_t* __restrict__ parts)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int e = arcs[i];
+    const int u = dag_src[e];
+    const int d = dag_ptr[u + 1] - dag_ptr[u];
+    parts[i] = d > kLightMaxDeg ? arc_parts(arc_c[e], k) : 1;
+}
+
+__global__ void list_items_kernel(int32_t n, const int32_t* __restrict__ parts, const int32_t* __restrict__ offs,
+                                  int32_t* __restrict__ items)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int P = parts[i];
+    const int o = offs[i];
+    for (int p = 0; p < P; ++p) {
+        items[2 * (o + p)] = (int32_t)i;
+        items[2 * (o + p) + 1] = p | (P << 16);
+    }
+}
+
+hipError_t launch_list_parts(const int32_t* arcs, int32_t n, const int32_t* dag_src, const int32_t* dag_ptr,
+                             const int32_t* arc_c, int32_t k, int32_t* parts, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    list_parts_kernel<<<(n + 255) / 256, 256, 0, s>>>(arcs, n, dag_src, dag_ptr, arc_c, k, parts);
+    return hipGetLastError();
+}
+
+hipError_t launch_list_items(int32_t n, const int32_t* parts, const int32_t* offs, int32_t* items, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    list_items_kernel<<<(n + 255) / 256, 256, 0, s>>>(n, parts, offs, items);
+    return hipGetLastError();
+}
+
+hipError_t launch_check_arcs(const int32_t* arcs, int32_t n, int64_t m, int32_t* err, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    check_arcs_kernel<<<(n + 255) / 256, 256, 0, s>>>(arcs, n, m, err);
+    return hipGetLastError();
+}
+
+hipError_t launch_gather_arc_c(const int32_t* arcs, int32_t n, const int32_t* arc_c, u64* out, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    gather_arc_c_kernel<<<(n + 255) / 256, 256, 0, s>>>(arcs, n, arc_c, out);
+    return hipGetLastError();
 }
 
 __global__ void fill_i32_kernel(int32_t* p, int32_t v, int64_t n)

@@ -9,6 +9,7 @@ import json
 import math
 import os
 import sys
+import time
 
 import numpy as np
 import pytest
@@ -153,6 +154,74 @@ def test_rmat14_per_arc(citron_gpu):
         assert [int(x) for x in per_arc[idx]] == gold["arcs"][str(k)], k
         if str(k) in gold["counts"]:
             assert total == gold["counts"][str(k)]["count"]
+
+
+def test_count_arcs_matches_per_arc(citron_gpu):
+    """List mode (citron_count_arcs) against the full per-arc count, on a
+    shuffled list with repeats; errors for bad indices."""
+    g = gg.config_graph("rmat14")
+    h = load(citron_gpu, g)
+    m = h.m
+    rng = np.random.default_rng(77)
+    arcs = np.concatenate([rng.permutation(m), rng.integers(0, m, 500)]).astype(np.int32)
+    for k in range(2, 9):
+        total, per_arc = h.count_per_arc(k)
+        got = h.count_arcs(k, arcs)
+        say("count_arcs k", k, int(got.sum(dtype=np.uint64)))
+        assert np.array_equal(got, per_arc[arcs]), k
+    assert h.count_arcs(5, np.zeros(0, np.int32)).size == 0
+    for bad in ([m], [-1], [0, m + 5]):
+        with pytest.raises(citron_gpu.CitronError):
+            h.count_arcs(5, np.array(bad, np.int32))
+
+
+_RMAT20 = {}
+
+
+def _rmat20(citron):
+    if "h" not in _RMAT20:
+        gold = _golden("rmat20")
+        g = gg.config_graph("rmat20")
+        assert g.sha256() == gold["sha256"]
+        _RMAT20.update(g=g, gold=gold, h=load(citron, g))
+    return _RMAT20["g"], _RMAT20["gold"], _RMAT20["h"]
+
+
+def test_rmat20_counts(citron_gpu):
+    """Full-size R-MAT scale 20: whole-graph counts against the oracle's."""
+    g, gold, h = _rmat20(citron_gpu)
+    assert h.info()["max_outdeg"] == gold["max_outdeg"]
+    for k, rec in gold["counts"].items():
+        say("rmat20 k", k)
+        assert h.count(int(k)) == rec["count"]
+
+
+def test_rmat20_per_arc_full_launch(citron_gpu):
+    """Full-size per-arc counts (the whole-graph launch) at the sampled arcs."""
+    g, gold, h = _rmat20(citron_gpu)
+    idx = np.array(gold["arcs"]["index"])
+    dptr, dcol = h.dag()
+    src = np.repeat(np.arange(g.n), np.diff(dptr))
+    assert list(src[idx]) == gold["arcs"]["u"] and list(dcol[idx]) == gold["arcs"]["v"]
+    for k in (5, 6):
+        say("rmat20 per-arc k", k)
+        total, per_arc = h.count_per_arc(k)
+        assert int(per_arc.sum(dtype=np.uint64)) == total
+        assert [int(x) for x in per_arc[idx]] == gold["arcs"][str(k)], k
+
+
+@pytest.mark.parametrize("k", [5, 6, 7, 8])
+def test_rmat20_sampled_arcs(citron_gpu, k):
+    """Full-size sampled arcs through the list-mode launch, up to k = 8."""
+    g, gold, h = _rmat20(citron_gpu)
+    idx = np.array(gold["arcs"]["index"], dtype=np.int32)
+    want = gold["arcs"][str(k)]
+    step = 32
+    for lo in range(0, len(idx), step):
+        t = time.perf_counter()
+        got = h.count_arcs(k, idx[lo:lo + step])
+        say(f"rmat20 count_arcs k={k} arcs {lo}..{lo + step - 1}: {time.perf_counter() - t:.2f} s")
+        assert [int(x) for x in got] == want[lo:lo + step], (k, lo)
 
 
 # -------------------------------------------------------------- invariants
