@@ -97,8 +97,9 @@ __device__ void wave_flush(u64 acc, int ovf, u64* dst, int32_t* ovf_dst)
     }
 }
 
-__device__ void wave_flush_stats(const u64* vals, u64* dst)
+__device__ __forceinline__ void wave_flush_stats(const u64* vals, u64* dst)
 {
+#pragma unroll
     for (int i = 0; i < kNumStats; ++i) {
         if ((i >= kStatWaveBusy && i <= kStatWaves) || i >= kStatWaveBusyMax) continue;   // written once per wave
         const u64 v = wave_sum_u64(vals[i]);
@@ -621,7 +622,8 @@ __device__ __forceinline__ void heavy_dfs(const HeavyCtx& H, u64 M, int need0, i
 }
 
 template <bool kStats, bool kPerArc>
-__device__ void heavy_arc(const HeavyCtx& H, int r, int part, int P, WaveBuf& wb, Acc& A, u64* per_arc)
+__device__ __forceinline__ void heavy_arc(const HeavyCtx& H, int r, int part, int P, WaveBuf& wb, Acc& A,
+                                          u64* per_arc)
 {
     const int q = lane_of();
     u64 uacc = 0;
@@ -682,6 +684,7 @@ __global__ void __launch_bounds__(kMaxBlock) count_kernel(KParams P)
     Acc A;
     A.acc = 0ull;
     A.ovf = 0;
+#pragma unroll
     for (int i = 0; i < kNumStats; ++i) A.st[i] = 0ull;
     int cur = -1;                      // query whose work the wave holds
     u64* per_arc = nullptr;
@@ -712,6 +715,7 @@ __global__ void __launch_bounds__(kMaxBlock) count_kernel(KParams P)
                 if (kStats) wave_flush_stats(A.st, oq.stats);
                 A.acc = 0ull;
                 A.ovf = 0;
+#pragma unroll
                 for (int i = 0; i < kNumStats; ++i) A.st[i] = 0ull;
             }
             cur = qi;
@@ -720,64 +724,60 @@ __global__ void __launch_bounds__(kMaxBlock) count_kernel(KParams P)
         const int i = q.item_lo + (g - q.item_begin);
         const int k = q.k;
         const u64 t_item = kStats ? wall_clock64() : 0ull;
+        // the item: one part of a heavy arc, or (a part of) a light vertex
+        int u, r = -1, part, nparts, tag;
+        bool heavy;
         if (q.arc_list) {
             // list mode: one part of one listed arc; counts go to its list slot
-            const int slot = q.arc_items[2 * i];
+            tag = q.arc_items[2 * i];
             const int pw = q.arc_items[2 * i + 1];
-            const int e = q.arc_list[slot];
-            const int u = q.dag_src[e];
-            const int a0 = q.dag_ptr[u];
-            const int d = q.dag_ptr[u + 1] - a0;
-            if (d > kLightMaxDeg) {
-                HeavyCtx H{q.rows.rows + q.rows.rows_off[u], (d + 63) >> 6, k - 1, slot};
-                heavy_arc<kStats, kPerArc>(H, e - a0, pw & 0xffff, pw >> 16, wb, A, per_arc);
-            } else {
-                if (wb.n + d > kWaveBufRows) flush_tasks<kStats, kPerArc>(wb, A, per_arc);
-                if (lane < d) {
-                    wb.rows[wb.n + lane] = q.rows.rows[q.rows.rows_off[u] + lane];
-                    wb.meta[wb.n + lane] = (wb.n << 8) | (k - 2);
-                    if (kPerArc) wb.tags[wb.n + lane] = slot;
-                }
-                if (lane == 0) wb.units[wb.nu] = wb.n + (e - a0);
-                wb.nu += 1;
-                wb.n += d;
-            }
-            if (wb.n >= P.flush_rows) flush_tasks<kStats, kPerArc>(wb, A, per_arc);
-            continue;
-        }
-        // bucket holding item i, then the arc or vertex and the part (part-major)
-        int lo = 0, hi = q.n_buckets - 1;
-        while (lo < hi) {
-            const int mid = (lo + hi + 1) >> 1;
-            if (q.buckets[4 * mid] <= i) lo = mid;
-            else hi = mid - 1;
-        }
-        const int key = q.buckets[4 * lo + 3] >> 1;
-        const bool light = (q.buckets[4 * lo + 3] & 1) != 0;
-        const int cnt = q.buckets[4 * lo + 2];
-        const int local = i - q.buckets[4 * lo];
-        const int part = local / cnt;
-        const int which = q.buckets[4 * lo + 1] + (local - part * cnt);
-        if (!light) {
-            const int P = arc_parts(key, k);
-            const int e = q.rows.harcs[which];
-            const int u = q.dag_src[e];
-            const int a0 = q.dag_ptr[u];
-            const int d = q.dag_ptr[u + 1] - a0;
-            HeavyCtx H{q.rows.rows + q.rows.rows_off[u], (d + 63) >> 6, k - 1, e};
-            heavy_arc<kStats, kPerArc>(H, e - a0, part, P, wb, A, per_arc);
+            const int e = q.arc_list[tag];
+            u = q.dag_src[e];
+            r = e - q.dag_ptr[u];
+            part = pw & 0xffff;
+            nparts = pw >> 16;
+            heavy = q.dag_ptr[u + 1] - q.dag_ptr[u] > kLightMaxDeg;
         } else {
-            const int P = light_parts(key + 1, k);
-            const int u = q.order[q.light_first + which];
-            const int a0 = q.dag_ptr[u];
-            const int d = q.dag_ptr[u + 1] - a0;
+            // bucket holding item i, then the arc or vertex and the part (part-major)
+            int lo = 0, hi = q.n_buckets - 1;
+            while (lo < hi) {
+                const int mid = (lo + hi + 1) >> 1;
+                if (q.buckets[4 * mid] <= i) lo = mid;
+                else hi = mid - 1;
+            }
+            const int key = q.buckets[4 * lo + 3] >> 1;
+            heavy = (q.buckets[4 * lo + 3] & 1) == 0;
+            const int cnt = q.buckets[4 * lo + 2];
+            const int local = i - q.buckets[4 * lo];
+            part = local / cnt;
+            const int which = q.buckets[4 * lo + 1] + (local - part * cnt);
+            if (heavy) {
+                const int e = q.rows.harcs[which];
+                u = q.dag_src[e];
+                r = e - q.dag_ptr[u];
+                nparts = arc_parts(key, k);
+                tag = e;
+            } else {
+                u = q.order[q.light_first + which];
+                nparts = light_parts(key + 1, k);
+                tag = -1;
+            }
+        }
+        const int a0 = q.dag_ptr[u];
+        const int d = q.dag_ptr[u + 1] - a0;
+        if (heavy) {
+            HeavyCtx H{q.rows.rows + q.rows.rows_off[u], (d + 63) >> 6, k - 1, tag};
+            heavy_arc<kStats, kPerArc>(H, r, part, nparts, wb, A, per_arc);
+        } else {
+            // rows of the vertex into the wave's buffer; the searched arcs
+            // (every nparts-th one, or the one listed) become units
             if (wb.n + d > kWaveBufRows) flush_tasks<kStats, kPerArc>(wb, A, per_arc);
             if (lane < d) {
                 wb.rows[wb.n + lane] = q.rows.rows[q.rows.rows_off[u] + lane];
                 wb.meta[wb.n + lane] = (wb.n << 8) | (k - 2);
-                if (kPerArc) wb.tags[wb.n + lane] = a0 + lane;
+                if (kPerArc) wb.tags[wb.n + lane] = tag < 0 ? a0 + lane : tag;
             }
-            const bool unit = lane < d && (P == 1 || lane % P == part);
+            const bool unit = lane < d && (r >= 0 ? lane == r : (nparts == 1 || lane % nparts == part));
             const u64 um = __ballot(unit);
             if (unit) wb.units[wb.nu + __popcll(um & (lane == 0 ? 0ull : (~0ull >> (kWave - lane))))] = wb.n + lane;
             wb.nu += __popcll(um);
