@@ -175,8 +175,14 @@ citron_status citron_get_tuning(const citron_graph* g, citron_tuning* t);
  *   [20] children with two levels left handled whole by one lane
  *   [21] work donations taken by idle lanes of the light engine
  *   [22] longest busy time of one wave (ticks)
- *   [23] longest single work item: (ticks << 32) | its index in the launch */
-#define CITRON_NSTATS 24
+ *   [23] longest single work item: (ticks << 32) | its index in the launch
+ *   [24] (scratch: waves resident at the end, 0)
+ *   [25] most waves resident at once
+ *   [26] shader-clock cycles of all waves, start to end; of these,
+ *        [27] in the light engine, [28] copying or compacting subgraphs,
+ *        [29] in lane-per-child two-level searches
+ *   [30], [31] reserved (0) */
+#define CITRON_NSTATS 32
 citron_status citron_work_stats(citron_graph* g, int32_t k, uint64_t* stats);
 
 void citron_free(citron_graph* g);       /* NULL is a no-op */

@@ -15,12 +15,13 @@ STATUS_NAMES = {0: "OK", 1: "EINVAL", 2: "ENOMEM", 3: "EOVERFLOW", 4: "EDEVICE",
                 5: "ESTATE", 6: "EBUSY"}
 DEVICE_PTRS = 1
 KMAX = 32
-NSTATS = 24
+NSTATS = 32
 STAT_NAMES = ["vertices", "rows", "entries", "word_ops", "pushes", "dag_bytes", "heavy_steps",
               "compactions", "compact_rows", "light_iters", "light_active", "light_units",
               "flushes", "heavy_leaf_cand", "light_pops", "wave_busy", "wave_first", "wave_last",
               "waves", "arc_lds", "need3_lanes",
-              "donations", "wave_busy_max", "item_max"]
+              "donations", "wave_busy_max", "item_max", "resident_now", "resident_max",
+              "cyc_total", "cyc_light", "cyc_copy", "cyc_need3", "reserved30", "reserved31"]
 
 _i32p = ctypes.POINTER(ctypes.c_int32)
 _u64p = ctypes.POINTER(ctypes.c_uint64)

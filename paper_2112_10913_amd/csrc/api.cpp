@@ -203,7 +203,11 @@ citron_status ensure_rows(citron_graph* g)
     if (!g->d_rows && (st = dalloc(&g->d_rows, (size_t)std::max<int64_t>(words, 1), acct, "subgraph rows")))
         return st;
     SmallDev* sd = g->d_small;
-    if ((e = launch_fill_u64(&sd->tri_acc, 0, 1, s)) != hipSuccess ||
+    // vertices of out-degree < 2 are not built (their arcs close no
+    // triangle): their rows and sizes must read as zero
+    if ((e = launch_fill_u64(g->d_rows, 0, std::max<int64_t>(words, 1), s)) != hipSuccess ||
+        (e = launch_fill_i32(g->d_arc_c, 0, g->m, s)) != hipSuccess ||
+        (e = launch_fill_u64(&sd->tri_acc, 0, 1, s)) != hipSuccess ||
         (e = launch_fill_i32(&sd->tri_ovf, 0, 2, s)) != hipSuccess ||
         (e = launch_fill_u64(sd->build_stats, 0, kNumStats, s)) != hipSuccess)
         return hip_fail(e, "fill");

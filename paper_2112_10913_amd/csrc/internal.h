@@ -39,7 +39,13 @@ enum StatSlot {
     kStatDonations = 21,   // light-engine work donations taken by idle lanes
     kStatWaveBusyMax = 22, // longest busy time of one wave (atomic max)
     kStatItemMax = 23,     // longest item: (ticks << 32) | item index (atomic max)
-    kNumStats = 24
+    kStatResidentNow = 24, // waves resident right now (live counter)
+    kStatResidentMax = 25, // most waves resident at once (atomic max)
+    kStatCycTotal = 26,    // shader-clock cycles of the waves, start to end
+    kStatCycLight = 27,    // ... of which in the light engine
+    kStatCycCopy = 28,     // ... of which copying or compacting subgraphs
+    kStatCycNeed3 = 29,    // ... of which in lane-per-child two-level searches
+    kNumStats = 32
 };
 
 // Schedule of one graph for the count kernel: vertices sorted by out-degree

@@ -41,6 +41,8 @@ constexpr int kLaneMaxWords = 4;        // multi-word masks a lane holds in regi
 constexpr int kDonateMinIdle = 8;       // idle lanes that trigger work donation
 constexpr int kBurstIters = 32;         // last-level steps of one leaf burst at most
 constexpr int kBurstMinLanes = 32;      // lanes at a last-level node to keep a burst going
+constexpr int kPosList = 512;           // candidate positions the mailbox area holds (2 KB)
+static_assert(kArcMaxC <= kPosList, "candidate positions of an LDS node fit the mailbox area");
 
 // ------------------------------------------------------------------ helpers
 
@@ -101,7 +103,8 @@ __device__ __forceinline__ void wave_flush_stats(const u64* vals, u64* dst)
 {
 #pragma unroll
     for (int i = 0; i < kNumStats; ++i) {
-        if ((i >= kStatWaveBusy && i <= kStatWaves) || i >= kStatWaveBusyMax) continue;   // written once per wave
+        // written once per wave at its end
+        if ((i >= kStatWaveBusy && i <= kStatWaves) || (i >= kStatWaveBusyMax && i <= kStatCycTotal)) continue;
         const u64 v = wave_sum_u64(vals[i]);
         if (lane_of() == 0 && v) atomicAdd(dst + i, v);
     }
@@ -148,7 +151,17 @@ __device__ __forceinline__ int wave_select(u64 m, int j, int W)
 // ------------------------------------------------------------------ layout
 
 __host__ __device__ inline int stack_levels(int max_k) { return max_k > 4 ? max_k - 4 : 1; }
-__host__ __device__ inline bool stack_in_lds(int max_k) { return stack_levels(max_k) <= kLdsStackLevels; }
+
+// Where the search stacks live, by the largest k of a launch: light stacks
+// in registers and heavy stacks in LDS (k <= 8), all in LDS (k <= 12), or
+// all in device memory.
+constexpr int kRegLevels = 4;
+enum StackMode { kStackReg = 0, kStackLds = 1, kStackGlobal = 2 };
+__host__ __device__ inline int stack_mode(int max_k)
+{
+    const int l = stack_levels(max_k);
+    return l <= kRegLevels ? kStackReg : (l <= kLdsStackLevels ? kStackLds : kStackGlobal);
+}
 // per wave: four stacks (light M/R, heavy M/R) of levels x 64 words
 __host__ __device__ inline int64_t wave_stack_words(int max_k) { return 4ll * stack_levels(max_k) * kWave; }
 __host__ __device__ inline int wave_lds_bytes(int max_k)
@@ -157,7 +170,9 @@ __host__ __device__ inline int wave_lds_bytes(int max_k)
     b += 8 * kArcWords;                                               // arc subgraph copy
     b += 32 * kWave;                                                  // donation mailbox
     b += 4 * kWaveBufRows;                                            // unit list
-    if (stack_in_lds(max_k)) b += 8 * (int)wave_stack_words(max_k);
+    const int mode = stack_mode(max_k);
+    if (mode == kStackReg) b += 8 * (int)wave_stack_words(max_k) / 2;   // heavy stacks only
+    if (mode == kStackLds) b += 8 * (int)wave_stack_words(max_k);
     return b;
 }
 
@@ -168,7 +183,7 @@ int32_t count_lds_bytes(int32_t, int32_t max_k, int32_t wg_waves)
 
 int64_t count_scratch_words(int32_t, int32_t max_k, int32_t wg_waves)
 {
-    if (stack_in_lds(max_k)) return 0;
+    if (stack_mode(max_k) != kStackGlobal) return 0;
     return ((int64_t)wg_waves * wave_stack_words(max_k) + 31) & ~31ll;
 }
 
@@ -200,14 +215,62 @@ struct WaveBuf {
     int nu;          // units in use (wave-uniform)
 };
 
-template <bool kStats, bool kPerArc>
+// Per-lane light stack: slot s holds the (M, R) pair of level s + 1.  In
+// registers (L > 0 levels, each access a select over the levels, since the
+// lanes sit at different depths) or in memory, one word per lane per level.
+template <int L>
+struct LightStack;
+
+template <>
+struct LightStack<4> {
+    u64 m0 = 0, m1 = 0, m2 = 0, m3 = 0, r0 = 0, r1 = 0, r2 = 0, r3 = 0;
+    __device__ __forceinline__ LightStack(const WaveBuf&) {}
+    __device__ __forceinline__ void put(int s, u64 M, u64 R)
+    {
+        m0 = s == 0 ? M : m0;
+        m1 = s == 1 ? M : m1;
+        m2 = s == 2 ? M : m2;
+        m3 = s == 3 ? M : m3;
+        r0 = s == 0 ? R : r0;
+        r1 = s == 1 ? R : r1;
+        r2 = s == 2 ? R : r2;
+        r3 = s == 3 ? R : r3;
+    }
+    __device__ __forceinline__ void set_r(int s, u64 R)
+    {
+        r0 = s == 0 ? R : r0;
+        r1 = s == 1 ? R : r1;
+        r2 = s == 2 ? R : r2;
+        r3 = s == 3 ? R : r3;
+    }
+    __device__ __forceinline__ u64 get_m(int s) const { return s == 0 ? m0 : s == 1 ? m1 : s == 2 ? m2 : m3; }
+    __device__ __forceinline__ u64 get_r(int s) const { return s == 0 ? r0 : s == 1 ? r1 : s == 2 ? r2 : r3; }
+};
+static_assert(kRegLevels == 4, "LightStack<4> holds the register levels");
+
+template <>
+struct LightStack<0> {
+    u64* __restrict__ sM;
+    u64* __restrict__ sR;
+    int lane;
+    __device__ __forceinline__ LightStack(const WaveBuf& wb) : sM(wb.sM), sR(wb.sR), lane(lane_of()) {}
+    __device__ __forceinline__ void put(int s, u64 M, u64 R)
+    {
+        sM[s * kWave + lane] = M;
+        sR[s * kWave + lane] = R;
+    }
+    __device__ __forceinline__ void set_r(int s, u64 R) { sR[s * kWave + lane] = R; }
+    __device__ __forceinline__ u64 get_m(int s) const { return sM[s * kWave + lane]; }
+    __device__ __forceinline__ u64 get_r(int s) const { return sR[s * kWave + lane]; }
+};
+
+template <bool kStats, bool kPerArc, int kRegL>
 __device__ __forceinline__ void light_engine(const WaveBuf& wb, Acc& A, u64* __restrict__ per_arc)
 {
     const int lane = lane_of();
     const u64 lt_mask = lane == 0 ? 0ull : (~0ull >> (kWave - lane));
     const u64* __restrict__ rows = wb.rows;
-    u64* __restrict__ sM = wb.sM;
-    u64* __restrict__ sR = wb.sR;
+    LightStack<kRegL> stk(wb);
     const int nunits = wb.nu;
     int next = 0;                      // wave-uniform unit counter
     bool active = false;
@@ -253,12 +316,12 @@ __device__ __forceinline__ void light_engine(const WaveBuf& wb, Acc& A, u64* __r
             u64 Ml = 0ull, Rl = 0ull;
             if (active) {
                 for (int l = 1; l <= t; ++l) {
-                    const u64 r = (l == t) ? R : sR[(l - 1) * kWave + lane];
+                    const u64 r = (l == t) ? R : stk.get_r(l - 1);
                     const int pc = __popcll(r);
                     if (pc >= 2 && (need + (t - l) >= 3 || pc >= 8)) {
                         lvl = l;
                         Rl = r;
-                        Ml = (l == t) ? M : sM[(l - 1) * kWave + lane];
+                        Ml = (l == t) ? M : stk.get_m(l - 1);
                         break;
                     }
                 }
@@ -274,7 +337,7 @@ __device__ __forceinline__ void light_engine(const WaveBuf& wb, Acc& A, u64* __r
                         const int p = select64(Rl, __popcll(Rl) / 2);
                         const u64 low = Rl & ((1ull << p) - 1);
                         if (lvl == t) R = low;
-                        else sR[(lvl - 1) * kWave + lane] = low;
+                        else stk.set_r(lvl - 1, low);
                         u64* mb = wb.mbox + 4 * recv;
                         mb[0] = Ml;
                         mb[1] = Rl & ~low;
@@ -327,8 +390,7 @@ __device__ __forceinline__ void light_engine(const WaveBuf& wb, Acc& A, u64* __r
                     R &= R - 1;
                     const u64 nm = M & rows[base + x];
                     if (__popcll(nm) >= need - 1) {
-                        sM[(t - 1) * kWave + lane] = M;
-                        sR[(t - 1) * kWave + lane] = R;
+                        stk.put(t - 1, M, R);
                         M = nm;
                         R = nm;
                         ++t;
@@ -370,22 +432,24 @@ __device__ __forceinline__ void light_engine(const WaveBuf& wb, Acc& A, u64* __r
                     --t;
                     ++need;
                     if (kStats) A.st[kStatLightPops] += 1;
-                    M = sM[(t - 1) * kWave + lane];
-                    R = sR[(t - 1) * kWave + lane];
+                    M = stk.get_m(t - 1);
+                    R = stk.get_r(t - 1);
                 }
             }
         }
     }
 }
 
-template <bool kStats, bool kPerArc>
+template <bool kStats, bool kPerArc, int kRegL>
 __device__ __forceinline__ void flush_tasks(WaveBuf& wb, Acc& A, u64* per_arc)
 {
     if (wb.n == 0) return;
     if (kStats && lane_of() == 0) A.st[kStatFlushes] += 1;
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
-    light_engine<kStats, kPerArc>(wb, A, per_arc);
+    const u64 c0 = kStats ? __builtin_readcyclecounter() : 0ull;
+    light_engine<kStats, kPerArc, kRegL>(wb, A, per_arc);
+    if (kStats && lane_of() == 0) A.st[kStatCycLight] += __builtin_readcyclecounter() - c0;
     __builtin_amdgcn_wave_barrier();
     wb.n = 0;
     wb.nu = 0;
@@ -393,65 +457,235 @@ __device__ __forceinline__ void flush_tasks(WaveBuf& wb, Acc& A, u64* per_arc)
 
 // ------------------------------------------------------------ heavy engine
 
-struct HeavyCtx {
-    const u64* __restrict__ rows;   // the source vertex's rows in device memory
-    int W;                          // words per row
-    int L;                          // vertices of the clique inside the subgraph (k - 1)
-    int tag;                        // the arc (per-arc output)
+typedef __attribute__((address_space(3))) u64 lds_u64;
+typedef __attribute__((address_space(3))) int32_t lds_i32;
+typedef __attribute__((address_space(1))) const u64 glb_u64;
+typedef __attribute__((address_space(1))) const unsigned char glb_u8;
+
+// Rows of a heavy subgraph: the source vertex's rows in device memory
+// (kGlobal), addressed with 32-bit offsets from a wave-uniform base, or a
+// compacted copy in the wave's LDS.
+template <bool kGlobal>
+struct RowRef;
+template <>
+struct RowRef<true> {
+    glb_u64* p;
+    __device__ __forceinline__ u64 operator()(unsigned i) const
+    {
+        return *reinterpret_cast<glb_u64*>(reinterpret_cast<glb_u8*>(p) + (i << 3));
+    }
+};
+template <>
+struct RowRef<false> {
+    const lds_u64* p;
+    __device__ __forceinline__ u64 operator()(unsigned i) const { return p[i]; }
 };
 
-// Handle a node with mask m (c candidates, `need` more vertices to choose).
-// Returns true when the caller must search it depth first (c > 64 and
-// need >= 3).
-template <bool kStats, bool kPerArc, bool kGlobal>
-__device__ __forceinline__ void heavy_dfs(const HeavyCtx& H, u64 M, int need0, int lvl0, int part, int P,
-                                          WaveBuf& wb, Acc& A, u64& uacc, u64* per_arc);
+template <bool kGlobal>
+struct HeavyCtx {
+    RowRef<kGlobal> rows;
+    int W;     // words per row
+    int L;     // vertices of the clique inside the subgraph (k - 1)
+    int tag;   // the arc (per-arc output)
+};
 
-// Copy the subgraph induced on the c candidates of m (rows in H, device
-// memory) to the wave's LDS buffer, compacted to W2 = ceil(c/64) words per
-// row: lane a rebuilds row a by extracting, word by word, the bits at the
-// candidates' positions.  c <= kArcMaxC.
-__device__ __forceinline__ int copy_to_lds(const HeavyCtx& H, u64 M, int c, u64* __restrict__ dst)
+// Parallel bit extract with a wave-uniform mask (Hacker's Delight, section
+// 7-4, "compress"): the masks are prepared once per mask word (scalar
+// work), then each lane packs its own word in six shift-and-merge steps.
+struct Pext {
+    u64 m, v0, v1, v2, v3, v4, v5;
+};
+
+__device__ __forceinline__ u64 prefix_xor64(u64 x)
+{
+    x ^= x << 1;
+    x ^= x << 2;
+    x ^= x << 4;
+    x ^= x << 8;
+    x ^= x << 16;
+    x ^= x << 32;
+    return x;
+}
+
+__device__ __forceinline__ Pext pext_prep(u64 m)
+{
+    Pext p;
+    p.m = m;
+    u64 mk = ~m << 1;
+    u64 v[6];
+#pragma unroll
+    for (int i = 0; i < 6; ++i) {
+        const u64 mp = prefix_xor64(mk);
+        v[i] = mp & m;
+        m = (m ^ v[i]) | (v[i] >> (1 << i));
+        mk &= ~mp;
+    }
+    p.v0 = v[0];
+    p.v1 = v[1];
+    p.v2 = v[2];
+    p.v3 = v[3];
+    p.v4 = v[4];
+    p.v5 = v[5];
+    return p;
+}
+
+__device__ __forceinline__ u64 pext_apply(u64 x, const Pext& p)
+{
+    u64 t;
+    x &= p.m;
+    t = x & p.v0; x = (x ^ t) | (t >> 1);
+    t = x & p.v1; x = (x ^ t) | (t >> 2);
+    t = x & p.v2; x = (x ^ t) | (t >> 4);
+    t = x & p.v3; x = (x ^ t) | (t >> 8);
+    t = x & p.v4; x = (x ^ t) | (t >> 16);
+    t = x & p.v5; x = (x ^ t) | (t >> 32);
+    return x;
+}
+
+// Row x of H restricted to the candidates of M (lane q holds word q of M)
+// and packed: bit i of the result is candidate i.  At most 256 candidates
+// (four words o0..o3).  Uniform control flow: the whole wave calls it.
+template <bool kGlobal>
+__device__ __forceinline__ void pack_row(const HeavyCtx<kGlobal>& H, u64 M, int x, bool valid, u64& o0, u64& o1,
+                                         u64& o2, u64& o3)
+{
+    o0 = o1 = o2 = o3 = 0ull;
+    const unsigned base = valid ? (unsigned)(x * H.W) : 0u;
+    int off = 0;
+    for (int w0 = 0; w0 < H.W; w0 += 4) {
+        // four source words in flight at a time
+        u64 src[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) src[i] = (valid && w0 + i < H.W) ? H.rows(base + w0 + i) : 0ull;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            if (w0 + i >= H.W) break;
+            const u64 mw = readlane64(M, w0 + i);
+            if (mw == 0ull) continue;
+            const u64 p = pext_apply(src[i], pext_prep(mw));
+            const int wi = off >> 6, sh = off & 63;
+            const u64 lo = p << sh;
+            const u64 hi = sh ? (p >> (64 - sh)) : 0ull;
+            // wi is wave-uniform; selects keep o0..o3 in registers
+            o0 |= wi == 0 ? lo : 0ull;
+            o1 |= (wi == 1 ? lo : 0ull) | (wi == 0 ? hi : 0ull);
+            o2 |= (wi == 2 ? lo : 0ull) | (wi == 1 ? hi : 0ull);
+            o3 |= (wi == 3 ? lo : 0ull) | (wi == 2 ? hi : 0ull);
+            off += __popcll(mw);
+        }
+    }
+}
+
+// Copy the subgraph induced on the c candidates of M to dst in LDS,
+// compacted to W2 = ceil(c / 64) words per row; c <= kArcMaxC.
+__device__ __forceinline__ int copy_to_lds(const HeavyCtx<true>& H, u64 M, int c, lds_u64* dst)
 {
     const int q = lane_of();
     const int W2 = (c + 63) >> 6;
     for (int a0 = 0; a0 < c; a0 += kWave) {
         const int a = a0 + q;
         const int xa = wave_select(M, a, H.W);
-        const u64* __restrict__ src = H.rows + (int64_t)(a < c ? xa : 0) * H.W;
-        unsigned o[8] = {0u, 0u, 0u, 0u, 0u, 0u, 0u, 0u};
-        int b = 0;
-        for (int w = 0; w < H.W; ++w) {
-            u64 mw = readlane64(M, w);
-            if (mw == 0ull) continue;
-            const u64 word = a < c ? src[w] : 0ull;
-            const unsigned wlo = (unsigned)word, whi = (unsigned)(word >> 32);
-            while (mw) {
-                const int p = __builtin_ctzll(mw);
-                mw &= mw - 1;
-                const unsigned bit = ((p < 32 ? wlo : whi) >> (p & 31)) & 1u;
-#pragma unroll
-                for (int h = 0; h < 8; ++h)
-                    if ((b >> 5) == h) o[h] |= bit << (b & 31);
-                ++b;
-            }
+        u64 o0, o1, o2, o3;
+        pack_row<true>(H, M, xa, a < c, o0, o1, o2, o3);
+        if (a < c) {
+            lds_u64* d = dst + a * W2;
+            d[0] = o0;
+            if (W2 > 1) d[1] = o1;
+            if (W2 > 2) d[2] = o2;
+            if (W2 > 3) d[3] = o3;
         }
-        if (a < c)
-            for (int i = 0; i < W2; ++i) dst[a * W2 + i] = ((u64)o[2 * i + 1] << 32) | o[2 * i];
     }
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     return W2;
 }
 
+// Two levels left on a node of the LDS copy with more than 64 candidates
+// (W words per row, W = 2..4): every lane takes a candidate x, forms its
+// child mask m AND row_x in registers and sums the last level of that
+// child itself, two vertices y of the child per step; a lane that finishes
+// takes the next candidate (positions listed in pos), so lanes stay busy
+// however uneven the children are.  Returns this lane's sum (< 2^24).
+template <int W, bool kStats>
+__device__ __forceinline__ unsigned need3_lanes(const HeavyCtx<false>& H, const u64* mw, int nj,
+                                                const lds_i32* pos, unsigned& took, unsigned& ops)
+{
+    const int lane = lane_of();
+    const u64 lt = lane == 0 ? 0ull : (~0ull >> (kWave - lane));
+    int next = 0;                 // wave-uniform: candidates handed out
+    bool act = false;
+    u64 ch[W];
+#pragma unroll
+    for (int i = 0; i < W; ++i) ch[i] = 0ull;
+    u64 r = 0ull;
+    int w = 0;
+    unsigned sum = 0;
+    for (;;) {
+        const u64 idle = __ballot(!act);
+        if (next < nj && (__popcll(idle) >= 8 || idle == ~0ull)) {
+            const int jj = next + __popcll(idle & lt);
+            next += __popcll(idle);
+            if (!act && jj < nj) {
+                const unsigned b = (unsigned)(pos[jj] * W);
+#pragma unroll
+                for (int i = 0; i < W; ++i) ch[i] = mw[i] & H.rows(b + i);
+                r = ch[0];
+                w = 0;
+                act = true;
+                if (kStats) ++took;
+            }
+        } else if (idle == ~0ull) {
+            break;
+        }
+        if (act) {
+#pragma unroll
+            for (int i = 1; i < W; ++i)
+                if (r == 0ull && w < i) {
+                    w = i;
+                    r = ch[i];
+                }
+            if (r == 0ull) {
+                act = false;
+            } else {
+                const int y1 = w * 64 + __builtin_ctzll(r);
+                r &= r - 1;
+                const bool two = r != 0ull;   // a second vertex of the same word
+                const int y2 = two ? w * 64 + __builtin_ctzll(r) : y1;
+                if (two) r &= r - 1;
+                const unsigned b1 = (unsigned)(y1 * W), b2 = (unsigned)(y2 * W);
+                u64 a1[W], a2[W];
+#pragma unroll
+                for (int i = 0; i < W; ++i) {
+                    a1[i] = H.rows(b1 + i);
+                    a2[i] = H.rows(b2 + i);
+                }
+                unsigned c1 = 0, c2 = 0;
+#pragma unroll
+                for (int i = 0; i < W; ++i) {
+                    c1 += __popcll(ch[i] & a1[i]);
+                    c2 += __popcll(ch[i] & a2[i]);
+                }
+                sum += c1 + (two ? c2 : 0u);
+                if (kStats) ops += two ? 2 * W : W;
+            }
+        }
+    }
+    return sum;
+}
+
+template <bool kStats, bool kPerArc, bool kGlobal, int kRegL>
+__device__ __forceinline__ void heavy_dfs(const HeavyCtx<kGlobal>& H, u64 M, int need0, int lvl0, int part, int P,
+                                          WaveBuf& wb, Acc& A, u64& uacc, u64* per_arc);
+
 // Handle a node with mask m (c candidates, `need` more vertices to choose;
 // rows in device memory when kGlobal, else in the wave's LDS copy).  Returns
 // true when the caller must search it depth first.  lvl is the first free
 // level of the heavy stacks.  Only first-level branches j = part (mod P)
-// of the node are taken (P > 1 at the root of a split arc only).
-template <bool kStats, bool kPerArc, bool kGlobal>
-__device__ __forceinline__ bool heavy_node(const HeavyCtx& H, u64 m, int c, int need, int lvl, int part, int P,
-                                           WaveBuf& wb, Acc& A, u64& uacc, u64* per_arc)
+// of the node are taken; P > 1 only at the root of a split arc, which has
+// need >= 4 (arc_parts is 1 for k <= 5).
+template <bool kStats, bool kPerArc, bool kGlobal, int kRegL>
+__device__ __forceinline__ bool heavy_node(const HeavyCtx<kGlobal>& H, u64 m, int c, int need, int lvl, int part,
+                                           int P, WaveBuf& wb, Acc& A, u64& uacc, u64* per_arc)
 {
     const int lane = lane_of();
     if (c < need) return false;
@@ -467,13 +701,14 @@ __device__ __forceinline__ bool heavy_node(const HeavyCtx& H, u64 m, int c, int 
         for (int j0 = 0; j0 < c; j0 += kWave) {
             const int j = j0 + lane;
             const int x = wave_select(m, j, H.W);
-            u64 s = 0;
-            if (j < c) {
-                const u64* __restrict__ rx = H.rows + (int64_t)x * H.W;
-                for (int w = 0; w < H.W; ++w) s += (u64)__popcll(readlane64(m, w) & rx[w]);
+            unsigned s = 0;
+            const unsigned b = (unsigned)((j < c ? x : 0) * H.W);
+            for (int w = 0; w < H.W; ++w) {
+                const u64 mw = readlane64(m, w);
+                if (j < c && mw) s += __popcll(mw & H.rows(b + w));
             }
-            A.acc += s;
-            if (kPerArc) uacc += s;
+            A.acc += (u64)s;
+            if (kPerArc) uacc += (u64)s;
             if (kStats && j < c) {
                 A.st[kStatWordOps] += H.W;
                 A.st[kStatHeavyLeafCand] += 1;
@@ -481,88 +716,65 @@ __device__ __forceinline__ bool heavy_node(const HeavyCtx& H, u64 m, int c, int 
         }
         return false;
     }
-    if (need == 3 && c > kWave && H.W <= kLaneMaxWords) {
-        // two levels left, many candidates: lane j takes the j-th candidate
-        // x, forms its child mask m AND row_x (at most 4 words, in
-        // registers) and sums the last level of that child itself
-        const int nj = (c - part + P - 1) / P;
-        for (int j0 = 0; j0 < nj; j0 += kWave) {
-            const int jj = j0 + lane;
-            const int j = jj < nj ? part + P * jj : c;
-            const int x = wave_select(m, j, H.W);
-            u64 ch[kLaneMaxWords];
-            const u64* __restrict__ rx = H.rows + (int64_t)(j < c ? x : 0) * H.W;
-#pragma unroll
-            for (int w = 0; w < kLaneMaxWords; ++w) {
-                ch[w] = 0ull;
-                if (w < H.W) {
-                    const u64 mw = readlane64(m, w);
-                    if (j < c) ch[w] = mw & rx[w];
-                }
-            }
-            u64 s = 0;
-            u64 ops = 0;
-#pragma unroll
-            for (int w = 0; w < kLaneMaxWords; ++w) {
-                if (w >= H.W) break;
-                u64 r = ch[w];
-                while (r != 0ull) {
-                    const int y = w * 64 + __builtin_ctzll(r);
-                    r &= r - 1;
-                    const u64* __restrict__ ry = H.rows + (int64_t)y * H.W;
-                    int cnt = 0;
-#pragma unroll
-                    for (int i = 0; i < kLaneMaxWords; ++i)
-                        if (i < H.W) cnt += __popcll(ch[i] & ry[i]);
-                    s += (u64)cnt;
-                    if (kStats) ops += H.W;
-                }
-            }
-            A.acc += s;
-            if (kPerArc) uacc += s;
-            if (kStats) {
-                A.st[kStatWordOps] += ops;
-                if (j < c) A.st[kStatNeed3Lanes] += 1;
-            }
-        }
-        return false;
-    }
-    if (kGlobal && need >= 3 && c <= kArcMaxC && c > kWave) {
+    if constexpr (kGlobal) {
+    if (c <= kArcMaxC && c > kWave) {
         // continue from an LDS copy of this node's subgraph
-        const int W2 = copy_to_lds(H, m, c, wb.arc);
-        const HeavyCtx HL{wb.arc, W2, H.L, H.tag};
+        const u64 c0 = kStats ? __builtin_readcyclecounter() : 0ull;
+        lds_u64* arc = (lds_u64*)wb.arc;
+        const int W2 = copy_to_lds(H, m, c, arc);
+        if (kStats && lane == 0) A.st[kStatCycCopy] += __builtin_readcyclecounter() - c0;
+        const HeavyCtx<false> HL{RowRef<false>{arc}, W2, H.L, H.tag};
         const int rem = c - 64 * lane;
         const u64 all = lane < W2 ? (rem >= 64 ? ~0ull : ((1ull << rem) - 1)) : 0ull;
         if (kStats && lane == 0) A.st[kStatArcLds] += 1;
-        if (heavy_node<kStats, kPerArc, false>(HL, all, c, need, lvl, part, P, wb, A, uacc, per_arc))
-            heavy_dfs<kStats, kPerArc, false>(HL, all, need, lvl, part, P, wb, A, uacc, per_arc);
+        if (heavy_node<kStats, kPerArc, false, kRegL>(HL, all, c, need, lvl, part, P, wb, A, uacc, per_arc))
+            heavy_dfs<kStats, kPerArc, false, kRegL>(HL, all, need, lvl, part, P, wb, A, uacc, per_arc);
         __builtin_amdgcn_wave_barrier();
         return false;
     }
-    if (c <= kWave) {
-        // compaction: lane a rebuilds row a over the c candidates by
-        // extracting, word by word, the bits at the candidates' positions
-        if (wb.n + c > kWaveBufRows) flush_tasks<kStats, kPerArc>(wb, A, per_arc);
-        const int xa = wave_select(m, lane, H.W);
-        const u64* __restrict__ ra = H.rows + (int64_t)(lane < c ? xa : 0) * H.W;
-        unsigned nlo = 0, nhi = 0;
-        int b = 0;
-        for (int w = 0; w < H.W; ++w) {
-            u64 mw = readlane64(m, w);
-            if (mw == 0ull) continue;
-            const u64 word = lane < c ? ra[w] : 0ull;
-            const unsigned wlo = (unsigned)word, whi = (unsigned)(word >> 32);
-            while (mw) {
-                const int p = __builtin_ctzll(mw);
-                mw &= mw - 1;
-                const unsigned bit = ((p < 32 ? wlo : whi) >> (p & 31)) & 1u;
-                if (b < 32) nlo |= bit << b;
-                else nhi |= bit << (b - 32);
-                ++b;
-            }
+    }
+    if constexpr (!kGlobal) {
+    if (need == 3 && c > kWave) {
+        const u64 c0 = kStats ? __builtin_readcyclecounter() : 0ull;
+        const int nj = (c - part + P - 1) / P;
+        // positions of the candidates taken, in the mailbox area (idle while
+        // the light engine is not running); nj <= c <= kArcMaxC <= kPosList
+        lds_i32* pos = (lds_i32*)wb.mbox;
+        for (int j0 = 0; j0 < nj; j0 += kWave) {
+            const int jj = j0 + lane;
+            const int x = wave_select(m, jj < nj ? part + P * jj : c, H.W);
+            if (jj < nj) pos[jj] = x;
         }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        u64 mw[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) mw[i] = i < H.W ? readlane64(m, i) : 0ull;
+        unsigned took = 0, ops = 0, sum;
+        if (H.W == 2) sum = need3_lanes<2, kStats>(H, mw, nj, pos, took, ops);
+        else if (H.W == 3) sum = need3_lanes<3, kStats>(H, mw, nj, pos, took, ops);
+        else sum = need3_lanes<4, kStats>(H, mw, nj, pos, took, ops);
+        __builtin_amdgcn_wave_barrier();
+        A.acc += (u64)sum;
+        if (kPerArc) uacc += (u64)sum;
+        if (kStats) {
+            A.st[kStatWordOps] += ops;
+            A.st[kStatNeed3Lanes] += took;
+            if (lane == 0) A.st[kStatCycNeed3] += __builtin_readcyclecounter() - c0;
+        }
+        return false;
+    }
+    }
+    if (c <= kWave) {
+        // compaction: lane a packs row a over the c candidates into one
+        // word and the node goes to the light engine's queue
+        if (wb.n + c > kWaveBufRows) flush_tasks<kStats, kPerArc, kRegL>(wb, A, per_arc);
+        const u64 c0 = kStats ? __builtin_readcyclecounter() : 0ull;
+        const int xa = wave_select(m, lane, H.W);
+        u64 o0, o1, o2, o3;
+        pack_row<kGlobal>(H, m, xa, lane < c, o0, o1, o2, o3);
         if (lane < c) {
-            wb.rows[wb.n + lane] = ((u64)nhi << 32) | nlo;
+            wb.rows[wb.n + lane] = o0;
             wb.meta[wb.n + lane] = (wb.n << 8) | (need - 1);
             if (kPerArc) wb.tags[wb.n + lane] = H.tag;
         }
@@ -574,6 +786,7 @@ __device__ __forceinline__ bool heavy_node(const HeavyCtx& H, u64 m, int c, int 
         if (kStats && lane == 0) {
             A.st[kStatCompactions] += 1;
             A.st[kStatCompactRows] += (u64)c;
+            A.st[kStatCycCopy] += __builtin_readcyclecounter() - c0;
         }
         return false;
     }
@@ -582,8 +795,8 @@ __device__ __forceinline__ bool heavy_node(const HeavyCtx& H, u64 m, int c, int 
 
 // Depth-first search, all lanes in step, below a node with mask M (more
 // than 64 candidates, need0 more vertices), rows in H; stack levels from lvl0.
-template <bool kStats, bool kPerArc, bool kGlobal>
-__device__ __forceinline__ void heavy_dfs(const HeavyCtx& H, u64 M, int need0, int lvl0, int part, int P,
+template <bool kStats, bool kPerArc, bool kGlobal, int kRegL>
+__device__ __forceinline__ void heavy_dfs(const HeavyCtx<kGlobal>& H, u64 M, int need0, int lvl0, int part, int P,
                                           WaveBuf& wb, Acc& A, u64& uacc, u64* per_arc)
 {
     const int q = lane_of();
@@ -607,10 +820,10 @@ __device__ __forceinline__ void heavy_dfs(const HeavyCtx& H, u64 M, int need0, i
             const int jr = jroot++;
             if (P > 1 && jr % P != part) continue;
         }
-        const u64 ch = M & (q < H.W ? H.rows[(int64_t)x * H.W + q] : 0ull);
+        const u64 ch = M & (q < H.W ? H.rows((unsigned)(x * H.W + q)) : 0ull);
         const int cc = wave_sum_small(__popcll(ch));
         if (kStats && q == 0) A.st[kStatHeavySteps] += 1;
-        if (heavy_node<kStats, kPerArc, kGlobal>(H, ch, cc, need0 - t, lvl0 + t, 0, 1, wb, A, uacc, per_arc)) {
+        if (heavy_node<kStats, kPerArc, kGlobal, kRegL>(H, ch, cc, need0 - t, lvl0 + t, 0, 1, wb, A, uacc, per_arc)) {
             wb.hM[(lvl0 + t - 1) * kWave + q] = M;
             wb.hR[(lvl0 + t - 1) * kWave + q] = R;
             M = ch;
@@ -621,17 +834,17 @@ __device__ __forceinline__ void heavy_dfs(const HeavyCtx& H, u64 M, int need0, i
     }
 }
 
-template <bool kStats, bool kPerArc>
-__device__ __forceinline__ void heavy_arc(const HeavyCtx& H, int r, int part, int P, WaveBuf& wb, Acc& A,
+template <bool kStats, bool kPerArc, int kRegL>
+__device__ __forceinline__ void heavy_arc(const HeavyCtx<true>& H, int r, int part, int P, WaveBuf& wb, Acc& A,
                                           u64* per_arc)
 {
     const int q = lane_of();
     u64 uacc = 0;
-    const u64 M = q < H.W ? H.rows[(int64_t)r * H.W + q] : 0ull;
+    const u64 M = q < H.W ? H.rows((unsigned)(r * H.W + q)) : 0ull;
     const int c = wave_sum_small(__popcll(M));
     const int need = H.L - 1;
-    if (heavy_node<kStats, kPerArc, true>(H, M, c, need, 0, part, P, wb, A, uacc, per_arc))
-        heavy_dfs<kStats, kPerArc, true>(H, M, need, 0, part, P, wb, A, uacc, per_arc);
+    if (heavy_node<kStats, kPerArc, true, kRegL>(H, M, c, need, 0, part, P, wb, A, uacc, per_arc))
+        heavy_dfs<kStats, kPerArc, true, kRegL>(H, M, need, 0, part, P, wb, A, uacc, per_arc);
     if (kPerArc) {
         const u64 s = wave_sum_u64(uacc);
         if (q == 0 && s) atomicAdd(per_arc + H.tag, s);
@@ -651,9 +864,10 @@ struct KParams {
     int32_t flush_rows;     // a wave runs its queue once it holds this many rows
 };
 
-template <bool kLdsStack, bool kStats, bool kPerArc>
+template <int kMode, bool kStats, bool kPerArc>
 __global__ void __launch_bounds__(kMaxBlock) count_kernel(KParams P)
 {
+    constexpr int kRegL = kMode == kStackReg ? kRegLevels : 0;
     extern __shared__ __align__(16) unsigned char smem[];
     const int lane = lane_of();
     const int wid = threadIdx.x / kWave;
@@ -668,16 +882,22 @@ __global__ void __launch_bounds__(kMaxBlock) count_kernel(KParams P)
     wb.mbox = reinterpret_cast<u64*>(wbase + 16 * kWaveBufRows + 8 * kArcWords);
     wb.units = reinterpret_cast<int32_t*>(wbase + 16 * kWaveBufRows + 8 * kArcWords + 32 * kWave);
     u64* stacks;
-    if (kLdsStack) {
-        stacks = reinterpret_cast<u64*>(wbase + 20 * kWaveBufRows + 8 * kArcWords + 32 * kWave);
-    } else {
+    if (kMode == kStackGlobal)
         stacks = P.scratch + (int64_t)blockIdx.x * P.scratch_words + (int64_t)wid * wave_stack_words(P.max_k);
-    }
+    else
+        stacks = reinterpret_cast<u64*>(wbase + 20 * kWaveBufRows + 8 * kArcWords + 32 * kWave);
     (void)nwaves;
-    wb.sM = stacks;
-    wb.sR = stacks + (int64_t)levels * kWave;
-    wb.hM = stacks + 2ll * levels * kWave;
-    wb.hR = stacks + 3ll * levels * kWave;
+    if (kMode == kStackReg) {
+        wb.sM = nullptr;
+        wb.sR = nullptr;
+        wb.hM = stacks;
+        wb.hR = stacks + (int64_t)levels * kWave;
+    } else {
+        wb.sM = stacks;
+        wb.sR = stacks + (int64_t)levels * kWave;
+        wb.hM = stacks + 2ll * levels * kWave;
+        wb.hR = stacks + 3ll * levels * kWave;
+    }
     wb.n = 0;
     wb.nu = 0;
 
@@ -689,6 +909,11 @@ __global__ void __launch_bounds__(kMaxBlock) count_kernel(KParams P)
     int cur = -1;                      // query whose work the wave holds
     u64* per_arc = nullptr;
     const u64 t_start = kStats ? wall_clock64() : 0ull;
+    const u64 cyc_start = kStats ? __builtin_readcyclecounter() : 0ull;
+    if (kStats && lane == 0) {
+        const u64 now = atomicAdd(P.queries[0].stats + kStatResidentNow, 1ull) + 1;
+        atomicMax(P.queries[0].stats + kStatResidentMax, now);
+    }
     u64 item_max = 0ull;
 
     for (;;) {
@@ -710,7 +935,7 @@ __global__ void __launch_bounds__(kMaxBlock) count_kernel(KParams P)
         if (qi != cur) {
             if (cur >= 0) {
                 const QueryDesc& oq = P.queries[cur];
-                flush_tasks<kStats, kPerArc>(wb, A, per_arc);
+                flush_tasks<kStats, kPerArc, kRegL>(wb, A, per_arc);
                 wave_flush(A.acc, A.ovf, oq.acc, oq.overflow);
                 if (kStats) wave_flush_stats(A.st, oq.stats);
                 A.acc = 0ull;
@@ -766,12 +991,13 @@ __global__ void __launch_bounds__(kMaxBlock) count_kernel(KParams P)
         const int a0 = q.dag_ptr[u];
         const int d = q.dag_ptr[u + 1] - a0;
         if (heavy) {
-            HeavyCtx H{q.rows.rows + q.rows.rows_off[u], (d + 63) >> 6, k - 1, tag};
-            heavy_arc<kStats, kPerArc>(H, r, part, nparts, wb, A, per_arc);
+            const HeavyCtx<true> H{RowRef<true>{(glb_u64*)(q.rows.rows + q.rows.rows_off[u])},
+                                   (d + 63) >> 6, k - 1, tag};
+            heavy_arc<kStats, kPerArc, kRegL>(H, r, part, nparts, wb, A, per_arc);
         } else {
             // rows of the vertex into the wave's buffer; the searched arcs
             // (every nparts-th one, or the one listed) become units
-            if (wb.n + d > kWaveBufRows) flush_tasks<kStats, kPerArc>(wb, A, per_arc);
+            if (wb.n + d > kWaveBufRows) flush_tasks<kStats, kPerArc, kRegL>(wb, A, per_arc);
             if (lane < d) {
                 wb.rows[wb.n + lane] = q.rows.rows[q.rows.rows_off[u] + lane];
                 wb.meta[wb.n + lane] = (wb.n << 8) | (k - 2);
@@ -783,7 +1009,7 @@ __global__ void __launch_bounds__(kMaxBlock) count_kernel(KParams P)
             wb.nu += __popcll(um);
             wb.n += d;
         }
-        if (wb.n >= P.flush_rows) flush_tasks<kStats, kPerArc>(wb, A, per_arc);
+        if (wb.n >= P.flush_rows) flush_tasks<kStats, kPerArc, kRegL>(wb, A, per_arc);
         if (kStats && lane == 0) {
             const u64 dt = wall_clock64() - t_item;
             if (dt > (item_max >> 32)) item_max = (dt << 32) | (u64)(unsigned)g;
@@ -791,7 +1017,7 @@ __global__ void __launch_bounds__(kMaxBlock) count_kernel(KParams P)
     }
     if (cur >= 0) {
         const QueryDesc& oq = P.queries[cur];
-        flush_tasks<kStats, kPerArc>(wb, A, per_arc);
+        flush_tasks<kStats, kPerArc, kRegL>(wb, A, per_arc);
         wave_flush(A.acc, A.ovf, oq.acc, oq.overflow);
         if (kStats) wave_flush_stats(A.st, oq.stats);
     }
@@ -805,19 +1031,33 @@ __global__ void __launch_bounds__(kMaxBlock) count_kernel(KParams P)
         atomicAdd(st + kStatWaves, 1ull);
         atomicMax(st + kStatWaveBusyMax, t_end - t_start);
         atomicMax(st + kStatItemMax, item_max);
+        atomicAdd(st + kStatCycTotal, __builtin_readcyclecounter() - cyc_start);
+        atomicAdd(st + kStatResidentNow, ~0ull);   // minus one
     }
 }
 
-template <bool kLdsStack, bool kStats, bool kPerArc>
+template <int kMode, bool kStats, bool kPerArc>
 static hipError_t launch_variant(const KParams& P, const CountLaunch& cl, hipStream_t s)
 {
-    const void* fn = (const void*)count_kernel<kLdsStack, kStats, kPerArc>;
+    const void* fn = (const void*)count_kernel<kMode, kStats, kPerArc>;
     if (cl.lds_bytes > 65536) {
         hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, cl.lds_bytes);
         if (e != hipSuccess) return e;
     }
-    count_kernel<kLdsStack, kStats, kPerArc><<<cl.blocks, cl.wg_waves * kWave, cl.lds_bytes, s>>>(P);
+    count_kernel<kMode, kStats, kPerArc><<<cl.blocks, cl.wg_waves * kWave, cl.lds_bytes, s>>>(P);
     return hipGetLastError();
+}
+
+template <int kMode>
+static hipError_t launch_mode(const KParams& P, const CountLaunch& cl, hipStream_t s)
+{
+    const int v = (cl.stats ? 2 : 0) | (cl.per_arc ? 1 : 0);
+    switch (v) {
+    case 0: return launch_variant<kMode, false, false>(P, cl, s);
+    case 1: return launch_variant<kMode, false, true>(P, cl, s);
+    case 2: return launch_variant<kMode, true, false>(P, cl, s);
+    default: return launch_variant<kMode, true, true>(P, cl, s);
+    }
 }
 
 hipError_t launch_count(const CountLaunch& cl, hipStream_t s)
@@ -833,17 +1073,10 @@ hipError_t launch_count(const CountLaunch& cl, hipStream_t s)
     P.scratch_words = cl.scratch_words;
     P.max_k = cl.max_k;
     P.flush_rows = cl.flush_rows;
-    const bool lds = stack_in_lds(cl.max_k);
-    const int v = (lds ? 4 : 0) | (cl.stats ? 2 : 0) | (cl.per_arc ? 1 : 0);
-    switch (v) {
-    case 0: return launch_variant<false, false, false>(P, cl, s);
-    case 1: return launch_variant<false, false, true>(P, cl, s);
-    case 2: return launch_variant<false, true, false>(P, cl, s);
-    case 3: return launch_variant<false, true, true>(P, cl, s);
-    case 4: return launch_variant<true, false, false>(P, cl, s);
-    case 5: return launch_variant<true, false, true>(P, cl, s);
-    case 6: return launch_variant<true, true, false>(P, cl, s);
-    default: return launch_variant<true, true, true>(P, cl, s);
+    switch (stack_mode(cl.max_k)) {
+    case kStackReg: return launch_mode<kStackReg>(P, cl, s);
+    case kStackLds: return launch_mode<kStackLds>(P, cl, s);
+    default: return launch_mode<kStackGlobal>(P, cl, s);
     }
 }
 

@@ -175,6 +175,31 @@ def test_count_arcs_matches_per_arc(citron_gpu):
             h.count_arcs(5, np.array(bad, np.int32))
 
 
+def test_outdegree_one_arcs_read_zero(citron_gpu):
+    """Arcs whose source has out-degree 1 close no triangle and are not
+    built; their sizes and rows must read as zero even in reused device
+    memory (a freed graph's rows are handed out again)."""
+    big = load(citron_gpu, gg.config_graph("rmat14"))
+    big.count(5)
+    big.free()
+    # a path, a star, a triangle and a K5: many out-degree-1 sources
+    n = 400
+    k5 = [(360 + a, 360 + b) for a in range(5) for b in range(a + 1, 5)]
+    src = list(range(0, 199)) + [200] * 150 + [350, 351, 352, 350] + [a for a, _ in k5]
+    dst = list(range(1, 200)) + list(range(201, 351)) + [351, 352, 350, 353] + [b for _, b in k5]
+    g = gg.csr_from_edges(n, np.array(src), np.array(dst), perm_seed=None, name="paths")
+    h = load(citron_gpu, g)
+    dptr, dcol = h.dag()
+    us = np.repeat(np.arange(g.n), np.diff(dptr)).astype(np.int32)
+    for k in (3, 4, 5):
+        want, ovf = oracle.count_arcs(g.n, dptr, dcol, k, us, dcol)
+        assert not ovf
+        total, per_arc = h.count_per_arc(k)
+        bad = np.flatnonzero(per_arc != want)
+        assert bad.size == 0, (k, h.info(), bad[:8], per_arc[bad[:8]], want[bad[:8]], us[bad[:8]], dcol[bad[:8]])
+        assert np.array_equal(h.count_arcs(k, np.arange(h.m, dtype=np.int32)), want), k
+
+
 _RMAT20 = {}
 
 
