@@ -273,3 +273,48 @@ def test_a_planted_mistake_is_caught():
     c_wrong, _ = oracle.count_dag(g.n, wrong_ptr, wrong_col, 3)
     assert c_right == math.comb(6, 3)
     assert c_wrong != math.comb(6, 3)
+
+
+def _arc_stats_by_definition(g, k):
+    """Per-arc work statistics from the undirected adjacency, by the
+    definitions: orientation by (degree, id), C_uv = N->(u) & N->(v)."""
+    adj = [set(g.col[g.row_ptr[u]:g.row_ptr[u + 1]].tolist()) for u in range(g.n)]
+    deg = [len(a) for a in adj]
+    out = [{v for v in adj[u] if (deg[u], u) < (deg[v], v)} for u in range(g.n)]
+    st = dict(arcs=0, sum_duv=0, sum_s=0, sum_dw=0, max_s=0, arcs_kept=0, kept_sum_duv=0,
+              kept_sum_s=0, kept_sum_dw=0, max_outdeg=max((len(o) for o in out), default=0))
+    hist = [0] * 33
+    for u in range(g.n):
+        for v in out[u]:
+            c = out[u] & out[v]
+            s = len(c)
+            duv = len(out[u]) + len(out[v])
+            dw = sum(len(out[w]) for w in c)
+            st["arcs"] += 1
+            st["sum_duv"] += duv
+            st["sum_s"] += s
+            st["sum_dw"] += dw
+            st["max_s"] = max(st["max_s"], s)
+            if s >= k - 2:
+                st["arcs_kept"] += 1
+                st["kept_sum_duv"] += duv
+                st["kept_sum_s"] += s
+                st["kept_sum_dw"] += dw
+            hist[s.bit_length()] += 1
+    return st, hist
+
+
+@pytest.mark.parametrize("seed", [1, 2, 3])
+def test_arc_stats_match_definitions(seed):
+    """Work statistics against a set-based restatement of Section III-B's
+    candidate sets; sum_s is the triangle count (trace(A^3)/6)."""
+    g = gg.rmat(9, 12, seed=600 + seed)
+    dptr, dcol = oracle.orient(g.n, g.row_ptr, g.col)
+    for k in (3, 5, 7):
+        st, hist = oracle.arc_stats(g.n, dptr, dcol, k)
+        want, want_hist = _arc_stats_by_definition(g, k)
+        assert st == want, k
+        assert hist == want_hist
+    a = sp.csr_matrix((np.ones(g.nnz), g.col, g.row_ptr), shape=(g.n, g.n))
+    assert st["sum_s"] == round((a @ a @ a).diagonal().sum() / 6)
+    assert st["arcs"] == g.m
