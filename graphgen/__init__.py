@@ -29,7 +29,7 @@ __all__ = [
     "CSR", "csr_from_edges", "rmat", "chung_lu", "erdos_renyi",
     "complete", "turan", "complete_bipartite", "wheel", "grid", "hypercube",
     "disjoint_cliques", "empty", "fig1_example", "relabel", "config_graph",
-    "CONFIGS",
+    "CONFIGS", "batch_suite", "serve_suite",
 ]
 
 
@@ -336,3 +336,51 @@ def config_graph(name: str) -> CSR:
     if kind == "chung_lu":
         return chung_lu(**cfg)
     raise KeyError(name)
+
+
+def _batch_member(args):
+    i, seed0, scale_max = args
+    rng = np.random.default_rng(seed0 + i)
+    if i % 2 == 0:
+        scale = int(rng.integers(8, scale_max + 1))
+        ef = int(rng.integers(8, 33))
+        g = rmat(scale, ef, seed=seed0 + i)
+        g.name = f"rmat{scale}_ef{ef}_s{seed0 + i}"
+    else:
+        n = int(rng.integers(1000, 50001))
+        deg = float(rng.uniform(10.0, 40.0))
+        g = erdos_renyi(n, deg, seed=seed0 + i)
+        g.name = f"er{n}_d{deg:.1f}_s{seed0 + i}"
+    return g
+
+
+def batch_suite(count: int = 512, seed0: int = 4000, scale_max: int = 16, workers: int = 1) -> list:
+    """Mixed batch of graphs: half R-MAT (scale U{8..scale_max}, edge factor
+    U{8..32}), half Erdos-Renyi (n U[1000, 50000], mean degree U[10, 40]),
+    graph i drawn from seed seed0 + i and the list shuffled by seed0.  The
+    result does not depend on ``workers`` (generator processes)."""
+    jobs = [(i, seed0, scale_max) for i in range(count)]
+    if workers > 1:
+        import multiprocessing as mp
+        with mp.get_context("spawn").Pool(workers) as pool:
+            out = pool.map(_batch_member, jobs, chunksize=4)
+    else:
+        out = [_batch_member(j) for j in jobs]
+    order = np.random.default_rng(seed0).permutation(count)
+    return [out[j] for j in order]
+
+
+def serve_suite(count: int = 64, seed0: int = 5000, scale_min: int = 12, scale_max: int = 20,
+                big=None) -> list:
+    """Resident graphs of the served form: count - 1 R-MAT graphs (scale
+    U{scale_min..scale_max}, edge factor 16, seed seed0 + i) plus ``big`` (by
+    default the Chung-Lu configuration graph)."""
+    out = []
+    for i in range(count - 1):
+        rng = np.random.default_rng(seed0 + i)
+        scale = int(rng.integers(scale_min, scale_max + 1))
+        g = rmat(scale, 16, seed=seed0 + i)
+        g.name = f"rmat{scale}_s{seed0 + i}"
+        out.append(g)
+    out.append(big if big is not None else config_graph("chunglu22"))
+    return out
