@@ -90,6 +90,149 @@ def traffic_per_launch(ks):
         return None
 
 
+def run_batch(args, citron, gg, torch):
+    """Batched form: a mixed suite of graphs, every graph queried at every k
+    of args.ks, in one persistent launch (replayed from its captured HIP
+    graph) against the same queries as sequential plain counts."""
+    from paper_2112_10913_amd.autotune import autotune
+    t = time.perf_counter()
+    graphs = gg.batch_suite(count=args.batch_graphs, seed0=4000, workers=16)
+    log(f"generated {len(graphs)} graphs, m = {sum(x.m for x in graphs)} in "
+        f"{time.perf_counter() - t:.1f} s")
+    hs = []
+    for i, x in enumerate(graphs):
+        h = citron.Graph.from_csr(x.row_ptr, x.col).order()
+        h.count(3)                       # subgraph rows built: resident graphs
+        hs.append(h)
+        if i % 64 == 63:
+            log(f"  loaded {i + 1} graphs")
+    torch.cuda.synchronize()
+    gs = [h for h in hs for _ in args.ks]
+    ks = [k for _ in hs for k in args.ks]
+    log(f"{len(ks)} queries; sequential plain counts")
+    t = time.perf_counter()
+    plain = [h.count(k) for h, k in zip(gs, ks)]
+    t_seq = time.perf_counter() - t
+    log(f"  sequential {t_seq:.2f} s; autotuning the batched launch")
+    space = {"wg_waves": [2, 4, 8], "blocks_per_cu": [1, 2, 4], "flush_rows": [128]}
+    best, report = autotune(gs, ks, space=space, reps=1, use_cache=False, log=log)
+    got = citron.count_batch(gs, ks, tuning=best)          # captured
+    reps = []
+    for r in range(args.steps):
+        t = time.perf_counter()
+        got = citron.count_batch(gs, ks, tuning=best)
+        reps.append(time.perf_counter() - t)
+        log(f"  batched replay {r + 1}: {reps[-1]:.3f} s")
+    if got != plain:
+        raise SystemExit("batched counts differ from plain counts")
+    t_b = float(np.median(reps))
+    line = {
+        "metric": "k-clique count time & edges/s per (graph,k); batched/served vs plain; p99 lat",
+        "form": "batched", "value": len(ks) / t_b, "unit": "queries/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": 1, "ms_per_step": t_b * 1e3, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "u64", "data": "synthetic",
+        "config": {"workload": f"batch of {len(graphs)} graphs (R-MAT scale 8..16, edge factor 8..32; "
+                               f"Erdos-Renyi n 1k..50k, mean degree 10..40; seeds 4000+i), "
+                               f"k = {args.ks}", "queries": len(ks),
+                   "edges_total": int(sum(x.m for x in graphs))},
+        "sequential_plain_s": t_seq, "batched_s": t_b, "speedup_vs_sequential": t_seq / t_b,
+        "counts_equal": True, "tuning": best.__dict__,
+        "autotune_trials": [(tr["tuning"]["wg_waves"], tr["tuning"]["blocks_per_cu"], tr["seconds"])
+                            for tr in report["trials"]],
+    }
+    print(json.dumps(line), flush=True)
+
+
+def run_serve(args, citron, gg, torch):
+    """Served form: resident graphs, Poisson arrivals of (graph, k) requests,
+    continuous batching; latency percentiles and counts/s, against the same
+    arrival trace served first-come-first-served by plain counts."""
+    t = time.perf_counter()
+    big = gg.config_graph("chunglu22") if args.serve_big else gg.rmat(17, 16, seed=17)
+    graphs = gg.serve_suite(count=args.serve_graphs, seed0=5000, scale_min=12,
+                            scale_max=args.serve_scale_max, big=big)
+    log(f"generated {len(graphs)} graphs in {time.perf_counter() - t:.1f} s")
+    hs = []
+    for x in graphs:
+        h = citron.Graph.from_csr(x.row_ptr, x.col).order()
+        h.count(3)
+        hs.append(h)
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(5999)
+    nreq = args.serve_requests
+    kmin, kmax = args.serve_k
+    req = [(int(rng.integers(len(hs))), int(rng.integers(kmin, kmax + 1))) for _ in range(nreq)]
+    # plain counts (the reference values and the per-request service times)
+    log("plain counts of every distinct request")
+    plain, svc = {}, {}
+    for gi, k in sorted(set(req)):
+        t = time.perf_counter()
+        plain[(gi, k)] = hs[gi].count(k)
+        svc[(gi, k)] = time.perf_counter() - t
+    srv = citron.Server(hbm_budget_bytes=8 << 30, max_slots=64)
+    ids = [srv.add_graph(h) for h in hs]
+
+    def serve(arrivals):
+        done = []
+        t0 = time.perf_counter()
+        i = 0
+        while len(done) < len(arrivals):
+            now = time.perf_counter() - t0
+            while i < len(arrivals) and arrivals[i] <= now:
+                gi, k = req[i]
+                srv.submit(ids[gi], k, i)
+                i += 1
+            done += srv.poll()
+            time.sleep(0.0002)
+        return done, time.perf_counter() - t0
+
+    # saturated throughput: every request at time 0
+    res, span = serve([0.0] * nreq)
+    sat = nreq / span
+    for r in res:
+        if r["status"] != 0 or r["count"] != plain[req[r["tag"]]]:
+            raise SystemExit(f"served result differs from plain: {r}")
+    log(f"saturated: {sat:.1f} requests/s")
+    points = []
+    for frac in args.serve_load:
+        lam = frac * sat
+        arr = np.cumsum(rng.exponential(1.0 / lam, nreq)).tolist()
+        res, span = serve(arr)
+        lat = []
+        for r in res:
+            gi, k = req[r["tag"]]
+            if r["status"] != 0 or r["count"] != plain[(gi, k)]:
+                raise SystemExit(f"served result differs from plain: {r}")
+            lat.append((r["t_done_ns"] - r["t_submit_ns"]) / 1e6)
+        # FIFO plain service of the same trace (one request at a time)
+        clock, fifo = 0.0, []
+        for j, a in enumerate(arr):
+            clock = max(clock, a) + svc[req[j]]
+            fifo.append((clock - a) * 1e3)
+        p = {"load": frac, "lambda_rps": lam, "served_rps": nreq / span,
+             "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
+             "fifo_plain_p50_ms": float(np.percentile(fifo, 50)),
+             "fifo_plain_p99_ms": float(np.percentile(fifo, 99)),
+             "fifo_plain_rps": nreq / clock}
+        log(f"  load {frac}: {p}")
+        points.append(p)
+    srv.close()
+    line = {
+        "metric": "k-clique count time & edges/s per (graph,k); batched/served vs plain; p99 lat",
+        "form": "served", "value": sat, "unit": "requests/s (saturated)", "n_gpus": 1,
+        "steps": len(points), "warmup": 0, "ms_per_step": None, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "u64", "data": "synthetic",
+        "config": {"workload": f"{len(graphs)} resident graphs (R-MAT scale 12..{args.serve_scale_max}, "
+                               f"edge factor 16, seeds 5000+i, plus "
+                               f"{'the Chung-Lu 2^22 graph' if args.serve_big else 'R-MAT scale 17'}), "
+                               f"Poisson arrivals, k uniform in {kmin}..{kmax}",
+                   "requests_per_point": nreq},
+        "fifo_plain_saturated_rps": nreq / sum(svc[r] for r in req),
+        "points": points, "counts_equal": True,
+    }
+    print(json.dumps(line), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -102,6 +245,18 @@ def main():
                     help="also run instrumented launches and report the kernel's work counters")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a 1 GiB device-to-device copy (reference for HBM counters)")
+    ap.add_argument("--form", choices=["plain", "batch", "serve"], default="plain",
+                    help="plain (default): the workload above; batch / serve: the batched and "
+                         "served forms against sequential plain counts")
+    ap.add_argument("--batch-graphs", type=int, default=512)
+    ap.add_argument("--serve-graphs", type=int, default=64)
+    ap.add_argument("--serve-requests", type=int, default=2000)
+    ap.add_argument("--serve-scale-max", type=int, default=16)
+    ap.add_argument("--serve-k", type=int, nargs=2, default=[3, 8],
+                    help="served requests draw k uniformly from this range")
+    ap.add_argument("--serve-big", action="store_true",
+                    help="the last served graph is the Chung-Lu 2^22 graph (else R-MAT scale 17)")
+    ap.add_argument("--serve-load", type=float, nargs="+", default=[0.5, 0.9])
     args = ap.parse_args()
     if args.calibrate_copy:
         import torch
@@ -127,6 +282,10 @@ def main():
     tiny = gg.rmat(8, 8, seed=1)
     citron.Graph.from_csr(tiny.row_ptr, tiny.col).order().count(4)
     torch.cuda.synchronize()
+    if args.form == "batch":
+        return run_batch(args, citron, gg, torch)
+    if args.form == "serve":
+        return run_serve(args, citron, gg, torch)
     t = time.perf_counter()
     g = gg.config_graph(args.workload)
     log(f"generated {args.workload}: n={g.n} m={g.m} in {time.perf_counter() - t:.1f} s")

@@ -181,7 +181,8 @@ citron_status citron_get_tuning(const citron_graph* g, citron_tuning* t);
  *   [26] shader-clock cycles of all waves, start to end; of these,
  *        [27] in the light engine, [28] copying or compacting subgraphs,
  *        [29] in lane-per-child two-level searches
- *   [30], [31] reserved (0) */
+ *   [30] nodes finished by lane-per-child two-level searches, [31] their
+ *        row-word operations had their rows been ceil(c / 64) words wide */
 #define CITRON_NSTATS 32
 citron_status citron_work_stats(citron_graph* g, int32_t k, uint64_t* stats);
 

@@ -21,7 +21,7 @@ STAT_NAMES = ["vertices", "rows", "entries", "word_ops", "pushes", "dag_bytes", 
               "flushes", "heavy_leaf_cand", "light_pops", "wave_busy", "wave_first", "wave_last",
               "waves", "arc_lds", "need3_lanes",
               "donations", "wave_busy_max", "item_max", "resident_now", "resident_max",
-              "cyc_total", "cyc_light", "cyc_copy", "cyc_need3", "reserved30", "reserved31"]
+              "cyc_total", "cyc_light", "cyc_copy", "cyc_need3", "need3_nodes", "need3_min_ops"]
 
 _i32p = ctypes.POINTER(ctypes.c_int32)
 _u64p = ctypes.POINTER(ctypes.c_uint64)

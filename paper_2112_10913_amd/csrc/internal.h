@@ -45,6 +45,8 @@ enum StatSlot {
     kStatCycLight = 27,    // ... of which in the light engine
     kStatCycCopy = 28,     // ... of which copying or compacting subgraphs
     kStatCycNeed3 = 29,    // ... of which in lane-per-child two-level searches
+    kStatNeed3Nodes = 30,  // nodes finished by lane-per-child two-level searches
+    kStatNeed3MinOps = 31, // their row-word operations had rows been ceil(c / 64) words wide
     kNumStats = 32
 };
 

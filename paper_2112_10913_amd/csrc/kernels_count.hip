@@ -41,6 +41,7 @@ constexpr int kLaneMaxWords = 4;        // multi-word masks a lane holds in regi
 constexpr int kDonateMinIdle = 8;       // idle lanes that trigger work donation
 constexpr int kBurstIters = 32;         // last-level steps of one leaf burst at most
 constexpr int kBurstMinLanes = 32;      // lanes at a last-level node to keep a burst going
+constexpr int kN3Burst = 4;             // two-level steps between refills of idle lanes
 constexpr int kPosList = 512;           // candidate positions the mailbox area holds (2 KB)
 static_assert(kArcMaxC <= kPosList, "candidate positions of an LDS node fit the mailbox area");
 
@@ -637,16 +638,21 @@ __device__ __forceinline__ unsigned need3_lanes(const HeavyCtx<false>& H, const 
         } else if (idle == ~0ull) {
             break;
         }
-        if (act) {
+        // a burst of steps between refills: lanes that finish early wait
+        // for the next refill (at most kN3Burst - 1 steps)
+        for (int it = 0; it < kN3Burst; ++it) {
+            if (act) {
+                if (r == 0ull) {
 #pragma unroll
-            for (int i = 1; i < W; ++i)
-                if (r == 0ull && w < i) {
-                    w = i;
-                    r = ch[i];
+                    for (int i = 1; i < W; ++i)
+                        if (r == 0ull && w < i) {
+                            w = i;
+                            r = ch[i];
+                        }
+                    if (r == 0ull) act = false;
                 }
-            if (r == 0ull) {
-                act = false;
-            } else {
+            }
+            if (act) {
                 const int y1 = w * 64 + __builtin_ctzll(r);
                 r &= r - 1;
                 const bool two = r != 0ull;   // a second vertex of the same word
@@ -754,6 +760,10 @@ __device__ __forceinline__ bool heavy_node(const HeavyCtx<kGlobal>& H, u64 m, in
         if (H.W == 2) sum = need3_lanes<2, kStats>(H, mw, nj, pos, took, ops);
         else if (H.W == 3) sum = need3_lanes<3, kStats>(H, mw, nj, pos, took, ops);
         else sum = need3_lanes<4, kStats>(H, mw, nj, pos, took, ops);
+        if (kStats) {
+            A.st[kStatNeed3MinOps] += (u64)(ops / H.W) * (u64)((c + 63) >> 6);
+            if (lane == 0) A.st[kStatNeed3Nodes] += 1;
+        }
         __builtin_amdgcn_wave_barrier();
         A.acc += (u64)sum;
         if (kPerArc) uacc += (u64)sum;
