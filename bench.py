@@ -90,15 +90,11 @@ def traffic_per_launch(ks):
         return None
 
 
-def run_batch(args, citron, gg, torch):
+def run_batch(args, citron, gg, torch, graphs):
     """Batched form: a mixed suite of graphs, every graph queried at every k
     of args.ks, in one persistent launch (replayed from its captured HIP
     graph) against the same queries as sequential plain counts."""
     from paper_2112_10913_amd.autotune import autotune
-    t = time.perf_counter()
-    graphs = gg.batch_suite(count=args.batch_graphs, seed0=4000, workers=16)
-    log(f"generated {len(graphs)} graphs, m = {sum(x.m for x in graphs)} in "
-        f"{time.perf_counter() - t:.1f} s")
     hs = []
     for i, x in enumerate(graphs):
         h = citron.Graph.from_csr(x.row_ptr, x.col).order()
@@ -111,11 +107,15 @@ def run_batch(args, citron, gg, torch):
     ks = [k for _ in hs for k in args.ks]
     log(f"{len(ks)} queries; sequential plain counts")
     t = time.perf_counter()
-    plain = [h.count(k) for h, k in zip(gs, ks)]
+    plain = []
+    for i, (h, k) in enumerate(zip(gs, ks)):
+        plain.append(h.count(k))
+        if i % 256 == 255:
+            log(f"  {i + 1} plain counts, {time.perf_counter() - t:.1f} s")
     t_seq = time.perf_counter() - t
     log(f"  sequential {t_seq:.2f} s; autotuning the batched launch")
-    space = {"wg_waves": [2, 4, 8], "blocks_per_cu": [1, 2, 4], "flush_rows": [128]}
-    best, report = autotune(gs, ks, space=space, reps=1, use_cache=False, log=log)
+    trials = [citron.Tuning(wg_waves=w, blocks_per_cu=b, flush_rows=128) for w, b in ((4, 2), (2, 4), (8, 1))]
+    best, report = autotune(gs, ks, tunings=trials, reps=1, use_cache=False, log=log)
     got = citron.count_batch(gs, ks, tuning=best)          # captured
     reps = []
     for r in range(args.steps):
@@ -165,7 +165,9 @@ def run_serve(args, citron, gg, torch):
     # plain counts (the reference values and the per-request service times)
     log("plain counts of every distinct request")
     plain, svc = {}, {}
-    for gi, k in sorted(set(req)):
+    for j, (gi, k) in enumerate(sorted(set(req))):
+        if j % 50 == 0:
+            log(f"  {j} distinct requests counted")
         t = time.perf_counter()
         plain[(gi, k)] = hs[gi].count(k)
         svc[(gi, k)] = time.perf_counter() - t
@@ -176,6 +178,7 @@ def run_serve(args, citron, gg, torch):
         done = []
         t0 = time.perf_counter()
         i = 0
+        shown = 0
         while len(done) < len(arrivals):
             now = time.perf_counter() - t0
             while i < len(arrivals) and arrivals[i] <= now:
@@ -183,6 +186,9 @@ def run_serve(args, citron, gg, torch):
                 srv.submit(ids[gi], k, i)
                 i += 1
             done += srv.poll()
+            if len(done) >= shown + 100:
+                shown = len(done) - len(done) % 100
+                log(f"    {len(done)} of {len(arrivals)} served, {time.perf_counter() - t0:.1f} s")
             time.sleep(0.0002)
         return done, time.perf_counter() - t0
 
@@ -250,7 +256,7 @@ def main():
                          "served forms against sequential plain counts")
     ap.add_argument("--batch-graphs", type=int, default=512)
     ap.add_argument("--serve-graphs", type=int, default=64)
-    ap.add_argument("--serve-requests", type=int, default=2000)
+    ap.add_argument("--serve-requests", type=int, default=600)
     ap.add_argument("--serve-scale-max", type=int, default=16)
     ap.add_argument("--serve-k", type=int, nargs=2, default=[3, 8],
                     help="served requests draw k uniformly from this range")
@@ -273,8 +279,16 @@ def main():
               "(--gpus 1)", file=sys.stderr)
         sys.exit(2)
 
-    import torch
     import graphgen as gg
+    pre = None
+    if args.form == "batch":
+        # generated before the GPU is touched (worker processes)
+        t = time.perf_counter()
+        pre = gg.batch_suite(count=args.batch_graphs, seed0=4000, workers=16)
+        log(f"generated {len(pre)} graphs, m = {sum(x.m for x in pre)} in "
+            f"{time.perf_counter() - t:.1f} s")
+
+    import torch
     import paper_2112_10913_amd as citron
 
     torch.cuda.set_device(0)
@@ -283,7 +297,7 @@ def main():
     citron.Graph.from_csr(tiny.row_ptr, tiny.col).order().count(4)
     torch.cuda.synchronize()
     if args.form == "batch":
-        return run_batch(args, citron, gg, torch)
+        return run_batch(args, citron, gg, torch, pre)
     if args.form == "serve":
         return run_serve(args, citron, gg, torch)
     t = time.perf_counter()

@@ -69,12 +69,13 @@ def _time(graphs, ks, t, reps):
 
 
 def autotune(graphs, ks, space=None, reps: int = 3, cache_path: str | None = None,
-             use_cache: bool = True, log=None):
+             use_cache: bool = True, log=None, tunings=None):
     """Fastest count-launch tuning for the queries (graphs[i], ks[i]).
 
-    Returns (Tuning, report); report lists every trial with its median
-    time in seconds (None when the launch was refused, e.g. LDS too small
-    for that shape)."""
+    The trials are ``tunings`` if given, else the product of ``space``
+    (a dict of lists over DEFAULT_SPACE's keys).  Returns (Tuning, report);
+    report lists every trial with its median time in seconds (None when the
+    launch was refused, e.g. LDS too small for that shape)."""
     dev = device_info()
     key = signature(graphs, ks)
     path = cache_path or default_cache_path()
@@ -89,7 +90,7 @@ def autotune(graphs, ks, space=None, reps: int = 3, cache_path: str | None = Non
     trials = []
     ref = None
     best = None
-    for t in candidates(space):
+    for t in (tunings if tunings is not None else candidates(space)):
         try:
             sec, counts = _time(graphs, ks, t, reps)
         except CitronError as e:

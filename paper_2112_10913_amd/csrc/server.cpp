@@ -1,15 +1,24 @@
 // Request server over resident graphs with continuous batching.
 //
-// A server owns one worker thread and one stream on the device that was
-// current when it was created.  Requests (graph, k) are queued by
-// citron_server_submit and admitted in arrival order as soon as an
-// in-flight slot is free and their device footprint fits the memory
-// budget.  The worker runs steps back to back: each step is one launch of
-// the persistent count kernel over a bounded slice of every admitted
-// request's remaining work items, so requests that arrive while others run
-// join at the next step and share the device with them, and a request that
-// finishes frees its slot for the next one.  Counts are exact integers, so
-// a request's count does not depend on which requests it shares steps with.
+// A server owns one worker thread on the device that was current when it
+// was created.  Requests (graph, k) are queued by citron_server_submit and
+// admitted in arrival order as soon as an in-flight slot is free and their
+// device footprint fits the memory budget.  The worker issues steps: each
+// step is one launch of the persistent count kernel over work items of
+// several admitted requests, so requests that arrive while others run join
+// the next step and share the device with them.  Two lanes keep small
+// requests from waiting behind large ones:
+//   - fast lane (one stream): requests with at most kFastItems items, whole;
+//   - heavy lane (two streams, steps pipelined): the remaining items of the
+//     larger requests in admission order, up to kHeavyStepItems per step,
+//     so that a step works on one or two graphs at a time (their rows stay
+//     in cache) and a long request proceeds in bounded steps between which
+//     fast steps get compute units; while one heavy step drains its last
+//     items the next one takes the freed units.
+// Steps of a lane retire in issue order; a request whose items have all
+// retired returns its count and frees its slot.  Counts are exact integers,
+// so a request's count does not depend on which requests it shares steps
+// with.
 #include "api_internal.h"
 
 #include <algorithm>
@@ -32,22 +41,39 @@ int64_t now_ns()
 
 struct Req {
     uint64_t tag = 0;
+    int64_t id = 0;
+    bool fast = false;        // fast lane: issued whole in one step
     int32_t gid = 0;
     int32_t k = 0;
     int64_t t_submit = 0;
     int64_t t_admit = 0;
     int32_t slot = -1;
     int32_t n_items = 0;
-    int32_t cursor = 0;
+    int32_t issued = 0;       // items handed to steps
+    int32_t retired = 0;      // items of retired steps
     int64_t footprint = 0;
-    bool fresh = true;        // accumulator not yet zeroed
     QueryDesc q;
 };
 
-// Items of one request per step, and of one step in total: small enough that
-// a step ends in milliseconds, large enough to fill the device.
-constexpr int32_t kItemsPerReq = 8192;
-constexpr int32_t kItemsPerStep = 65536;
+// Lanes: a request with at most kFastItems items goes whole into one fast
+// step (at most kFastStepItems items); larger ones are sliced into heavy
+// steps of at most kItemsPerStep items, kItemsPerReq per request.
+constexpr int32_t kFastItems = 4096;
+constexpr int32_t kFastStepItems = 65536;
+constexpr int32_t kHeavyStepItems = 65536;
+constexpr int kInflight = 3;              // step 0: fast lane; 1, 2: heavy lane
+
+// One step's launch resources (reused once the step has retired).
+struct Step {
+    hipStream_t stream = nullptr;
+    hipEvent_t done = nullptr;
+    QueryDesc* d_q = nullptr;            // max_slots descriptors
+    QueryDesc* h_q = nullptr;            // pinned staging of the same
+    int32_t* d_item_ctr = nullptr;
+    unsigned long long* d_scratch = nullptr;
+    std::vector<std::pair<int64_t, int32_t>> parts;   // (request id, items)
+    hipError_t err = hipSuccess;
+};
 
 }  // namespace
 
@@ -71,17 +97,16 @@ struct citron_server {
     bool stop = false;
     std::thread worker;
 
-    // device: per slot accumulator and flag, the step's query table, the cursor
+    // device: per slot accumulator and flag; the steps' launch resources
     unsigned long long* d_acc = nullptr;
     int32_t* d_ovf = nullptr;
-    int32_t* d_item_ctr = nullptr;
-    QueryDesc* d_q = nullptr;
-    unsigned long long* d_scratch = nullptr;
     int64_t scratch_words = 0;
-    // pinned host mirrors
-    QueryDesc* h_q = nullptr;
+    Step steps[kInflight];
+    hipStream_t ctl = nullptr;            // slot resets and result reads
+    // pinned host mirrors of the slot results
     unsigned long long* h_acc = nullptr;
     int32_t* h_ovf = nullptr;
+    int64_t next_id = 0;
     std::string worker_error;
 };
 
@@ -113,17 +138,88 @@ void complete(citron_server* s, Req& r, uint64_t count, citron_status st)
     s->done.push_back(res);
 }
 
+// Launch one step of a lane.  Fast: every fast request not yet issued,
+// whole, up to kFastStepItems items.  Heavy: a slice of every heavy request
+// with items left.  Returns false when the lane has nothing to issue.
+bool issue_step(citron_server* s, Step& st, bool fast, int wg, int32_t blocks)
+{
+    int32_t with_work = 0;
+    for (const Req& r : s->active)
+        if (r.fast == fast && r.issued < r.n_items) ++with_work;
+    if (with_work == 0) return false;
+    const int32_t cap = fast ? kFastStepItems : kHeavyStepItems;
+    int32_t total = 0, maxk = 4, nq = 0;
+    st.parts.clear();
+    for (Req& r : s->active) {   // admission order
+        if (r.fast != fast || r.issued >= r.n_items) continue;
+        if (total >= cap) break;
+        int32_t take = r.n_items - r.issued;
+        if (fast && total + take > cap && total > 0) break;
+        if (!fast) take = std::min(take, cap - total);
+        QueryDesc q = r.q;
+        q.item_begin = total;
+        q.item_lo = r.issued;
+        q.n_items = take;
+        st.h_q[nq++] = q;
+        st.parts.emplace_back(r.id, take);
+        r.issued += take;
+        total += take;
+        maxk = std::max(maxk, r.k);
+    }
+    hipError_t e = launch_fill_i32(st.d_item_ctr, 0, 1, st.stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(st.d_q, st.h_q, sizeof(QueryDesc) * (size_t)nq, hipMemcpyHostToDevice, st.stream);
+    if (e == hipSuccess) {
+        CountLaunch cl;
+        cl.queries = st.d_q;
+        cl.n_queries = nq;
+        cl.total_items = total;
+        cl.item_ctr = st.d_item_ctr;
+        cl.scratch = st.d_scratch;
+        cl.scratch_words = s->scratch_words;
+        cl.max_k = maxk;
+        cl.blocks = blocks;
+        cl.wg_waves = wg;
+        cl.lds_bytes = count_lds_bytes(0, maxk, wg);
+        cl.flush_rows = s->tuning.flush_rows;
+        cl.stats = false;
+        cl.per_arc = false;
+        e = launch_count(cl, st.stream);
+    }
+    if (e == hipSuccess) e = hipEventRecord(st.done, st.stream);
+    st.err = e;
+    return true;
+}
+
+// Retire a step: credit its items to their requests.
+void retire_step(citron_server* s, Step& st)
+{
+    hipError_t e = st.err;
+    if (e == hipSuccess) e = hipEventSynchronize(st.done);
+    for (const auto& pr : st.parts)
+        for (Req& r : s->active)
+            if (r.id == pr.first) r.retired = (e == hipSuccess && r.retired >= 0) ? r.retired + pr.second : -1;
+    if (e != hipSuccess) s->worker_error = hipGetErrorString(e);
+    st.parts.clear();
+}
+
 void worker_main(citron_server* s)
 {
     (void)hipSetDevice(s->device);
     const int wg = s->tuning.wg_waves;
     const int32_t blocks = device_cus(s->device) * s->tuning.blocks_per_cu;
+    bool fast_busy = false;                   // step 0
+    std::deque<int> heavy_inflight;           // steps 1, 2 in issue order
+    std::vector<int> heavy_free = {2, 1};
     for (;;) {
         std::vector<int32_t> fresh_slots;
         {
             std::unique_lock<std::mutex> lock(s->mu);
-            s->cv.wait(lock, [&] { return s->stop || !s->pending.empty() || !s->active.empty(); });
-            if (s->stop) return;
+            s->cv.wait(lock, [&] {
+                return s->stop || !s->pending.empty() || !s->active.empty() || fast_busy ||
+                       !heavy_inflight.empty();
+            });
+            if (s->stop) break;
             // admission, in arrival order
             while (!s->pending.empty()) {
                 Req& r = s->pending.front();
@@ -166,98 +262,113 @@ void worker_main(citron_server* s)
                 s->free_slots.pop_back();
                 s->used += r.footprint;
                 r.t_admit = now_ns();
+                r.id = s->next_id++;
                 r.q = make_query(g, r.k, s->d_acc + r.slot, s->d_ovf + r.slot, nullptr, nullptr, 0);
                 r.n_items = r.q.n_items;
-                r.cursor = 0;
+                r.fast = r.n_items <= kFastItems;
+                r.issued = 0;
+                r.retired = 0;
                 fresh_slots.push_back(r.slot);
                 s->active.push_back(r);
                 s->pending.pop_front();
             }
-            if (s->active.empty()) continue;
+            s->cv.notify_all();
         }
-        // one step over a slice of every active request (the worker owns
-        // `active` outside the lock; submit only touches `pending`)
-        int32_t total = 0, maxk = 4, nq = 0;
-        const int32_t per_req =
-            std::max<int32_t>(64, std::min<int32_t>(kItemsPerReq, kItemsPerStep / (int32_t)s->active.size()));
-        std::vector<int32_t> take(s->active.size(), 0);
-        for (size_t i = 0; i < s->active.size(); ++i) {
-            Req& r = s->active[i];
-            take[i] = std::min(per_req, r.n_items - r.cursor);
-            QueryDesc q = r.q;
-            q.item_begin = total;
-            q.item_lo = r.cursor;
-            q.n_items = take[i];
-            s->h_q[nq++] = q;
-            total += take[i];
-            maxk = std::max(maxk, r.k);
+        // the worker owns `active` and the steps outside the lock; submit
+        // only touches `pending`
+        if (!fresh_slots.empty()) {
+            // zero the new slots before any step can touch them
+            hipError_t e = hipSuccess;
+            for (int32_t slot : fresh_slots) {
+                if (e == hipSuccess) e = launch_fill_u64(s->d_acc + slot, 0, 1, s->ctl);
+                if (e == hipSuccess) e = launch_fill_i32(s->d_ovf + slot, 0, 1, s->ctl);
+            }
+            if (e == hipSuccess) e = hipStreamSynchronize(s->ctl);
+            if (e != hipSuccess) s->worker_error = hipGetErrorString(e);
+        }
+        // issue what the lanes can take
+        if (!fast_busy && issue_step(s, s->steps[0], true, wg, blocks)) fast_busy = true;
+        while (!heavy_free.empty() && issue_step(s, s->steps[heavy_free.back()], false, wg, blocks)) {
+            heavy_inflight.push_back(heavy_free.back());
+            heavy_free.pop_back();
+        }
+        // retire finished steps; wait (polling, so that arrivals are admitted
+        // meanwhile) only when nothing finished and nothing else can be done
+        bool retired = false;
+        for (;;) {
+            if (fast_busy && (s->steps[0].err != hipSuccess || hipEventQuery(s->steps[0].done) != hipErrorNotReady)) {
+                retire_step(s, s->steps[0]);
+                fast_busy = false;
+                retired = true;
+            }
+            while (!heavy_inflight.empty()) {
+                Step& st = s->steps[heavy_inflight.front()];
+                if (st.err == hipSuccess && hipEventQuery(st.done) == hipErrorNotReady) break;
+                retire_step(s, st);
+                heavy_free.push_back(heavy_inflight.front());
+                heavy_inflight.pop_front();
+                retired = true;
+            }
+            if (retired || (!fast_busy && heavy_inflight.empty())) break;
+            {
+                std::lock_guard<std::mutex> lock(s->mu);
+                if (s->stop) break;
+                if (!s->pending.empty() && !s->free_slots.empty() &&
+                    s->used + footprint_of(s, s->pending.front().k) <= s->budget)
+                    break;   // admit, then issue
+            }
+            std::this_thread::sleep_for(std::chrono::microseconds(50));
+        }
+        // requests whose items have all retired
+        std::vector<Req> still;
+        std::vector<Req> fin;
+        for (Req& r : s->active) {
+            if (r.retired == r.n_items || r.retired < 0) fin.push_back(r);
+            else still.push_back(r);
         }
         hipError_t e = hipSuccess;
-        for (int32_t slot : fresh_slots) {
-            if (e == hipSuccess) e = launch_fill_u64(s->d_acc + slot, 0, 1, s->stream);
-            if (e == hipSuccess) e = launch_fill_i32(s->d_ovf + slot, 0, 1, s->stream);
+        for (const Req& r : fin) {
+            if (r.retired < 0) continue;
+            if (e == hipSuccess)
+                e = hipMemcpyAsync(s->h_acc + r.slot, s->d_acc + r.slot, sizeof(unsigned long long),
+                                   hipMemcpyDeviceToHost, s->ctl);
+            if (e == hipSuccess)
+                e = hipMemcpyAsync(s->h_ovf + r.slot, s->d_ovf + r.slot, sizeof(int32_t), hipMemcpyDeviceToHost,
+                                   s->ctl);
         }
-        if (e == hipSuccess) e = launch_fill_i32(s->d_item_ctr, 0, 1, s->stream);
-        if (e == hipSuccess)
-            e = hipMemcpyAsync(s->d_q, s->h_q, sizeof(QueryDesc) * (size_t)nq, hipMemcpyHostToDevice, s->stream);
-        if (e == hipSuccess && total > 0) {
-            CountLaunch cl;
-            cl.queries = s->d_q;
-            cl.n_queries = nq;
-            cl.total_items = total;
-            cl.item_ctr = s->d_item_ctr;
-            cl.scratch = s->d_scratch;
-            cl.scratch_words = s->scratch_words;
-            cl.max_k = maxk;
-            cl.blocks = blocks;
-            cl.wg_waves = wg;
-            cl.lds_bytes = count_lds_bytes(0, maxk, wg);
-            cl.flush_rows = s->tuning.flush_rows;
-            cl.stats = false;
-            cl.per_arc = false;
-            e = launch_count(cl, s->stream);
-        }
-        if (e == hipSuccess)
-            e = hipMemcpyAsync(s->h_acc, s->d_acc, sizeof(unsigned long long) * (size_t)s->max_slots,
-                               hipMemcpyDeviceToHost, s->stream);
-        if (e == hipSuccess)
-            e = hipMemcpyAsync(s->h_ovf, s->d_ovf, sizeof(int32_t) * (size_t)s->max_slots, hipMemcpyDeviceToHost,
-                               s->stream);
-        if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
+        if (!fin.empty() && e == hipSuccess) e = hipStreamSynchronize(s->ctl);
+        if (e != hipSuccess) s->worker_error = hipGetErrorString(e);
         std::lock_guard<std::mutex> lock(s->mu);
-        std::vector<Req> still;
-        for (size_t i = 0; i < s->active.size(); ++i) {
-            Req& r = s->active[i];
-            if (e != hipSuccess) {
-                s->worker_error = hipGetErrorString(e);
-                complete(s, r, 0, CITRON_EDEVICE);
-            } else {
-                r.cursor += take[i];
-                if (r.cursor < r.n_items) {
-                    still.push_back(r);
-                    continue;
-                }
-                complete(s, r, s->h_acc[r.slot], s->h_ovf[r.slot] ? CITRON_EOVERFLOW : CITRON_OK);
-            }
+        for (Req& r : fin) {
+            if (r.retired < 0 || e != hipSuccess) complete(s, r, 0, CITRON_EDEVICE);
+            else complete(s, r, s->h_acc[r.slot], s->h_ovf[r.slot] ? CITRON_EOVERFLOW : CITRON_OK);
             s->free_slots.push_back(r.slot);
             s->used -= r.footprint;
         }
         s->active.swap(still);
         s->cv.notify_all();
     }
+    // stop: let the steps in flight finish before their buffers are freed
+    if (fast_busy) (void)hipEventSynchronize(s->steps[0].done);
+    for (int si : heavy_inflight) (void)hipEventSynchronize(s->steps[si].done);
 }
 
 void server_free(citron_server* s)
 {
+    for (Step& st : s->steps) {
+        if (st.stream) (void)hipStreamSynchronize(st.stream);
+        if (st.d_q) (void)hipFree(st.d_q);
+        if (st.h_q) (void)hipHostFree(st.h_q);
+        if (st.d_item_ctr) (void)hipFree(st.d_item_ctr);
+        if (st.d_scratch) (void)hipFree(st.d_scratch);
+        if (st.done) (void)hipEventDestroy(st.done);
+        if (st.stream) (void)hipStreamDestroy(st.stream);
+    }
     if (s->d_acc) (void)hipFree(s->d_acc);
     if (s->d_ovf) (void)hipFree(s->d_ovf);
-    if (s->d_item_ctr) (void)hipFree(s->d_item_ctr);
-    if (s->d_q) (void)hipFree(s->d_q);
-    if (s->d_scratch) (void)hipFree(s->d_scratch);
-    if (s->h_q) (void)hipHostFree(s->h_q);
     if (s->h_acc) (void)hipHostFree(s->h_acc);
     if (s->h_ovf) (void)hipHostFree(s->h_ovf);
-    if (s->stream) (void)hipStreamDestroy(s->stream);
+    if (s->ctl) (void)hipStreamDestroy(s->ctl);
     delete s;
 }
 
@@ -275,20 +386,24 @@ citron_server* citron_server_create(int64_t hbm_budget_bytes, int32_t max_slots,
     s->budget = hbm_budget_bytes;
     s->max_slots = max_slots;
     hipError_t e = hipGetDevice(&s->device);
-    if (e == hipSuccess) e = hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking);
-    // deepest supported k sizes the shared stack scratch
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&s->ctl, hipStreamNonBlocking);
+    // deepest supported k sizes the stack scratch of each step
     const int32_t blocks = device_cus(s->device) * s->tuning.blocks_per_cu;
     s->scratch_words = count_scratch_words(0, CITRON_KMAX, s->tuning.wg_waves);
     if (e == hipSuccess) e = hipMalloc((void**)&s->d_acc, sizeof(unsigned long long) * (size_t)max_slots);
     if (e == hipSuccess) e = hipMalloc((void**)&s->d_ovf, sizeof(int32_t) * (size_t)max_slots);
-    if (e == hipSuccess) e = hipMalloc((void**)&s->d_item_ctr, sizeof(int32_t));
-    if (e == hipSuccess) e = hipMalloc((void**)&s->d_q, sizeof(QueryDesc) * (size_t)max_slots);
-    if (e == hipSuccess)
-        e = hipMalloc((void**)&s->d_scratch, (size_t)(s->scratch_words * 8 * blocks));
-    if (e == hipSuccess) e = hipHostMalloc((void**)&s->h_q, sizeof(QueryDesc) * (size_t)max_slots, hipHostMallocDefault);
     if (e == hipSuccess)
         e = hipHostMalloc((void**)&s->h_acc, sizeof(unsigned long long) * (size_t)max_slots, hipHostMallocDefault);
     if (e == hipSuccess) e = hipHostMalloc((void**)&s->h_ovf, sizeof(int32_t) * (size_t)max_slots, hipHostMallocDefault);
+    for (Step& st : s->steps) {
+        if (e == hipSuccess) e = hipStreamCreateWithFlags(&st.stream, hipStreamNonBlocking);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&st.done, hipEventDisableTiming);
+        if (e == hipSuccess) e = hipMalloc((void**)&st.d_q, sizeof(QueryDesc) * (size_t)max_slots);
+        if (e == hipSuccess)
+            e = hipHostMalloc((void**)&st.h_q, sizeof(QueryDesc) * (size_t)max_slots, hipHostMallocDefault);
+        if (e == hipSuccess) e = hipMalloc((void**)&st.d_item_ctr, sizeof(int32_t));
+        if (e == hipSuccess) e = hipMalloc((void**)&st.d_scratch, (size_t)(s->scratch_words * 8 * blocks));
+    }
     if (e != hipSuccess) {
         hip_fail(e, "server set-up");
         server_free(s);
@@ -362,7 +477,6 @@ void citron_server_destroy(citron_server* s)
         s->cv.notify_all();
     }
     if (s->worker.joinable()) s->worker.join();
-    (void)hipStreamSynchronize(s->stream);
     server_free(s);
 }
 
