@@ -32,6 +32,12 @@ sys.path.insert(0, ROOT)
 
 import numpy as np  # noqa: E402
 
+WORKLOADS = {
+    "rmat14": "R-MAT scale 14, edge factor 16, a/b/c/d 0.57/0.19/0.19/0.05, seed 14",
+    "rmat20": "R-MAT scale 20, edge factor 16, a/b/c/d 0.57/0.19/0.19/0.05, seed 20",
+    "chunglu22": "Chung-Lu, 2^22 vertices, degree exponent 2.1, mean degree 25, max weight 2e4, "
+                 "plus 2,000 planted cliques of size 10..40 (seeds 22, 2201)",
+}
 PEAK_HBM_GBS = 8000.0
 # int32 VALU lane-ops per second: 256 CUs x 64 lanes x 2.4 GHz
 PEAK_VALU_TOPS = 256 * 64 * 2.4e9 / 1e12
@@ -247,6 +253,9 @@ def main():
     ap.add_argument("--workload", default="rmat20")
     ap.add_argument("--ks", type=int, nargs="+", default=[5, 6, 7])
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--parts", type=int, default=1,
+                    help="run each count as this many strided shares of its work items "
+                         "(one launch each, progress after each); for counts of many minutes")
     ap.add_argument("--stats", action="store_true",
                     help="also run instrumented launches and report the kernel's work counters")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -321,7 +330,19 @@ def main():
             a = torch.cuda.Event(enable_timing=True)
             b = torch.cuda.Event(enable_timing=True)
             a.record()
-            counts[k] = h.count_checked(k)
+            if args.parts > 1:
+                # the count as strided shares of its work items, one launch
+                # each (progress after each share; the shares add up)
+                tot, ovf = 0, False
+                for p in range(args.parts):
+                    v, o = h.count_part(k, p, args.parts)
+                    tot += v
+                    ovf |= o
+                    torch.cuda.synchronize()
+                    log(f"    k={k} share {p + 1}/{args.parts} done")
+                counts[k] = (tot % 2**64, ovf or tot >= 2**64)
+            else:
+                counts[k] = h.count_checked(k)
             b.record()
             ev[k] = (a, b)
             b.synchronize()
@@ -400,9 +421,7 @@ def main():
         "value": value, "unit": "edges/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "u64", "data": "synthetic",
-        "config": {"workload": f"{args.workload}: R-MAT scale 20, edge factor 16, a/b/c/d "
-                               "0.57/0.19/0.19/0.05, seed 20" if args.workload == "rmat20"
-                   else args.workload,
+        "config": {"workload": f"{args.workload}: " + WORKLOADS.get(args.workload, args.workload),
                    "n": g.n, "m": m, "ks": args.ks, "max_outdeg": info["max_outdeg"],
                    "parallelism": "single GPU"},
         "t_order_ms_mean": float(np.mean(order_ms)),

@@ -97,11 +97,11 @@ def csr_from_edges(n: int, src, dst, perm_seed: int | None = None,
     key = np.unique(lo * n + hi)
     lo = key // n
     hi = key % n
-    both_src = np.concatenate([lo, hi])
-    both_dst = np.concatenate([hi, lo])
-    order = np.lexsort((both_dst, both_src))
-    both_src = both_src[order]
-    both_dst = both_dst[order]
+    # both directions, sorted by (source, destination) as one int64 key
+    both = np.concatenate([key, hi * n + lo])
+    both.sort(kind="stable")
+    both_src = both // n
+    both_dst = both - both_src * n
     if both_dst.size >= 2**31:
         raise ValueError("too many edges for int32 CSR")
     counts = np.bincount(both_src, minlength=n) if n else np.zeros(0, np.int64)
@@ -158,7 +158,7 @@ def _chung_lu_weights(n: int, gamma: float, mean: float, w_max: float) -> np.nda
         return float(np.mean(w_max * (i0 / (idx + i0)) ** expo))
 
     lo, hi = 1e-6, float(n)
-    for _ in range(200):
+    for _ in range(64):        # the bracket is down to adjacent doubles by then
         mid = np.sqrt(lo * hi)
         if mean_for(mid) < mean:
             lo = mid
@@ -189,9 +189,12 @@ def chung_lu(n: int = 1 << 22, gamma: float = 2.1, mean_degree: float = 25.0,
     chunk = 1 << 24
     done = 0
     while done < samples:
+        # inverse-CDF lookups of sorted uniforms (fast), then the second
+        # endpoints put in random order: the pairs are then independent
+        # draws, as with unsorted uniforms
         k = min(chunk, samples - done)
-        s = np.searchsorted(cdf, rng.random(k), side="right")
-        d = np.searchsorted(cdf, rng.random(k), side="right")
+        s = np.searchsorted(cdf, np.sort(rng.random(k)), side="right")
+        d = np.searchsorted(cdf, np.sort(rng.random(k)), side="right")[rng.permutation(k)]
         parts_s.append(np.minimum(s, n - 1))
         parts_d.append(np.minimum(d, n - 1))
         done += k

@@ -115,6 +115,16 @@ uint64_t citron_count(citron_graph* g, int32_t k, citron_status* st);
 uint64_t citron_count_per_arc(citron_graph* g, int32_t k, uint64_t* per_arc,
                               citron_status* st);
 
+/* One of nparts disjoint shares of citron_count(g, k): the work items
+ * part, part + nparts, part + 2 nparts, ... of the count's cost-ordered
+ * schedule (each item is one part of a heavy arc or of a light vertex; the
+ * k-cliques are the sum over arcs of Section III-B's edge-rooted counts, so
+ * the shares add up to the count, mod 2^64).  For progress reporting and
+ * for splitting a long count over several calls.  0 <= part < nparts,
+ * else CITRON_EINVAL; k <= 3 and trivial k give the whole value in part 0
+ * and 0 elsewhere.  Synchronous on the graph's stream. */
+uint64_t citron_count_part(citron_graph* g, int32_t k, int32_t part, int32_t nparts, citron_status* st);
+
 /* Edge-rooted counts of selected arcs (Section III-B: the k-cliques rooted
  * at an edge are the (k-2)-cliques of the subgraph induced by the common
  * out-neighbours of its endpoints): out[i] = the number of k-cliques whose

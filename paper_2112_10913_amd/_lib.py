@@ -97,6 +97,8 @@ def load_library():
     lib.citron_count.restype = ctypes.c_uint64
     lib.citron_count_per_arc.argtypes = [vp, ctypes.c_int32, vp, _i32p]
     lib.citron_count_per_arc.restype = ctypes.c_uint64
+    lib.citron_count_part.argtypes = [vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, _i32p]
+    lib.citron_count_part.restype = ctypes.c_uint64
     lib.citron_count_arcs.argtypes = [vp, ctypes.c_int32, vp, ctypes.c_int32, vp, _i32p]
     lib.citron_count_arcs.restype = ctypes.c_uint64
     lib.citron_count_batch.argtypes = [ctypes.POINTER(vp), _i32p, ctypes.c_int32, _u64p, _i32p,
@@ -252,6 +254,14 @@ class Graph:
             raise _err(st.value)
         arr = buf[:self.m].cpu().numpy().view(np.uint64)
         return int(v), arr
+
+    def count_part(self, k: int, part: int, nparts: int) -> tuple[int, bool]:
+        """(share, overflow) of the count: work items part (mod nparts)."""
+        st = ctypes.c_int32(0)
+        v = load_library().citron_count_part(self._handle(), int(k), int(part), int(nparts), ctypes.byref(st))
+        if st.value not in (OK, EOVERFLOW):
+            raise _err(st.value)
+        return int(v), st.value == EOVERFLOW
 
     def count_arcs(self, k: int, arcs) -> np.ndarray:
         """Edge-rooted k-clique counts of the listed DAG arcs (uint64 array)."""

@@ -341,6 +341,7 @@ QueryDesc make_query(const citron_graph* g, int32_t k, unsigned long long* acc, 
     q.n_work = g->n_work[k];
     q.item_begin = item_begin;
     q.n_items = q.n_work;
+    q.item_stride = 1;
     return q;
 }
 
@@ -397,7 +398,8 @@ struct ListItems {
 
 // One query through the count kernel; synchronous on the graph's stream.
 static citron_status run_single(citron_graph* g, int32_t k, unsigned long long* per_arc, bool stats,
-                                uint64_t* out_count, const int32_t* arc_list = nullptr, int32_t n_list = 0)
+                                uint64_t* out_count, const int32_t* arc_list = nullptr, int32_t n_list = 0,
+                                int32_t part = 0, int32_t nparts = 1)
 {
     std::lock_guard<std::mutex> lock(g->mu);
     hipError_t e = hipSetDevice(g->device);
@@ -413,6 +415,10 @@ static citron_status run_single(citron_graph* g, int32_t k, unsigned long long* 
         if (e == hipSuccess) e = hipStreamSynchronize(s);
         if (e != hipSuccess) return hip_fail(e, "per-arc copy");
         *out_count = 0;   // the caller sums the listed arcs
+        return CITRON_OK;
+    }
+    if (k == 3 && part != 0) {   // a strided part of the triangle sum: all in part 0
+        *out_count = 0;
         return CITRON_OK;
     }
     if (k == 3) {
@@ -451,6 +457,13 @@ static citron_status run_single(citron_graph* g, int32_t k, unsigned long long* 
         return hip_fail(e, "fill");
     g->h_small->query = make_query(g, k, &sd->acc, &sd->overflow, per_arc, stats ? g->d_stats : nullptr, 0);
     ListItems li;
+    if (nparts > 1) {
+        // items part, part + nparts, part + 2 nparts, ... of the schedule
+        QueryDesc& q = g->h_small->query;
+        q.item_lo = part;
+        q.item_stride = nparts;
+        q.n_items = q.n_work > part ? (q.n_work - part + nparts - 1) / nparts : 0;
+    }
     if (arc_list) {
         // items of the listed arcs: heavy ones split into parts like the full schedule
         st = li.build(g, arc_list, n_list, k, s);
@@ -625,6 +638,25 @@ uint64_t citron_count(citron_graph* g, int32_t k, citron_status* st_out)
     if (trivial) return v;
     uint64_t c = 0;
     *st = run_single(g, k, nullptr, false, &c);
+    if (*st && *st != CITRON_EOVERFLOW) return 0;
+    return c;
+}
+
+uint64_t citron_count_part(citron_graph* g, int32_t k, int32_t part, int32_t nparts, citron_status* st_out)
+{
+    citron_status dummy;
+    citron_status* st = st_out ? st_out : &dummy;
+    if (nparts < 1 || part < 0 || part >= nparts) {
+        *st = fail(CITRON_EINVAL, "part must be in 0..nparts-1");
+        return 0;
+    }
+    bool trivial;
+    uint64_t v;
+    *st = check_count_args(g, k, &trivial, &v);
+    if (*st) return 0;
+    if (trivial) return part == 0 ? v : 0;
+    uint64_t c = 0;
+    *st = run_single(g, k, nullptr, false, &c, nullptr, 0, part, nparts);
     if (*st && *st != CITRON_EOVERFLOW) return 0;
     return c;
 }

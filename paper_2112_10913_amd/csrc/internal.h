@@ -100,7 +100,7 @@ struct QueryDesc {
     int32_t item_begin;          // first global item of this query
     int32_t n_items;             // items of this query in the launch
     int32_t item_lo;             // local index of the query's first item in the launch
-    int32_t pad;
+    int32_t item_stride;         // local item of launch item g: item_lo + (g - item_begin) * item_stride
     // list mode (arc_list != nullptr): item j is (slot, part) = (arc_items[2j],
     // arc_items[2j+1] & 0xffff) of arc arc_list[slot], split into
     // arc_items[2j+1] >> 16 parts; its counts go to per-arc slot `slot`

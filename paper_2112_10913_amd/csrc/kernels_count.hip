@@ -265,6 +265,22 @@ struct LightStack<0> {
     __device__ __forceinline__ u64 get_r(int s) const { return sR[s * kWave + lane]; }
 };
 
+// One degrees-only step on a last-level node: the next two candidates x of
+// R (R != 0) leave R, and the result is the sum of popcount(M AND row_x).
+// Without a second candidate the first row is read twice and counted once
+// (no branch).
+__device__ __forceinline__ unsigned leaf_step(const u64* __restrict__ rows, int base, u64 M, u64& R)
+{
+    const int x1 = __builtin_ctzll(R);
+    R &= R - 1;
+    const bool two = R != 0ull;
+    const int x2 = two ? __builtin_ctzll(R) : x1;
+    R &= R - 1;                        // stays 0 when it was 0
+    const u64 r1 = rows[base + x1];
+    const u64 r2 = rows[base + x2];
+    return (unsigned)__popcll(M & r1) + (two ? (unsigned)__popcll(M & r2) : 0u);
+}
+
 template <bool kStats, bool kPerArc, int kRegL>
 __device__ __forceinline__ void light_engine(const WaveBuf& wb, Acc& A, u64* __restrict__ per_arc)
 {
@@ -371,21 +387,10 @@ __device__ __forceinline__ void light_engine(const WaveBuf& wb, Acc& A, u64* __r
             if (R != 0ull) {
                 if (need == 2) {
                     // degrees-only last level, two candidates per step
-                    const int x1 = __builtin_ctzll(R);
-                    R &= R - 1;
-                    const u64 r1 = rows[base + x1];
-                    u64 r2 = 0ull;
-                    int two = 0;
-                    if (R != 0ull) {
-                        const int x2 = __builtin_ctzll(R);
-                        R &= R - 1;
-                        r2 = rows[base + x2];
-                        two = 1;
-                    }
-                    const u64 c = (u64)(__popcll(M & r1) + __popcll(M & r2));
-                    A.acc += c;
-                    if (kPerArc) uacc += c;
-                    if (kStats) A.st[kStatWordOps] += 1 + two;
+                    const unsigned c = leaf_step(rows, base, M, R);
+                    A.acc += (u64)c;
+                    if (kPerArc) uacc += (u64)c;
+                    if (kStats) A.st[kStatWordOps] += 2;
                 } else {
                     const int x = __builtin_ctzll(R);
                     R &= R - 1;
@@ -403,27 +408,17 @@ __device__ __forceinline__ void light_engine(const WaveBuf& wb, Acc& A, u64* __r
             if (need == 2 && R != 0ull) {
                 // leaf burst: while most lanes sit at a last-level node, run
                 // only last-level steps, two candidates at a time
+                unsigned bacc = 0;             // <= 2 * 64 * kBurstIters
                 for (int it = 0; it < kBurstIters; ++it) {
                     const bool leaf = R != 0ull;
                     if (__popcll(__ballot(leaf)) < kBurstMinLanes) break;
                     if (leaf) {
-                        const int x1 = __builtin_ctzll(R);
-                        R &= R - 1;
-                        const u64 r1 = rows[base + x1];
-                        u64 r2 = 0ull;
-                        int two = 0;
-                        if (R != 0ull) {
-                            const int x2 = __builtin_ctzll(R);
-                            R &= R - 1;
-                            r2 = rows[base + x2];
-                            two = 1;
-                        }
-                        const u64 c = (u64)(__popcll(M & r1) + __popcll(M & r2));
-                        A.acc += c;
-                        if (kPerArc) uacc += c;
-                        if (kStats) A.st[kStatWordOps] += 1 + two;
+                        bacc += leaf_step(rows, base, M, R);
+                        if (kStats) A.st[kStatWordOps] += 2;
                     }
                 }
+                A.acc += (u64)bacc;
+                if (kPerArc) uacc += (u64)bacc;
             }
             if (R == 0ull) {
                 if (t == 1) {
@@ -956,7 +951,7 @@ __global__ void __launch_bounds__(kMaxBlock) count_kernel(KParams P)
             cur = qi;
             per_arc = q.per_arc;
         }
-        const int i = q.item_lo + (g - q.item_begin);
+        const int i = q.item_lo + (g - q.item_begin) * q.item_stride;
         const int k = q.k;
         const u64 t_item = kStats ? wall_clock64() : 0ull;
         // the item: one part of a heavy arc, or (a part of) a light vertex

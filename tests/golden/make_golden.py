@@ -8,6 +8,7 @@ Per-arc values are the edge-rooted counts of a seeded sample of arcs.
 
     python tests/golden/make_golden.py rmat14          # counts k = 3..6
     python tests/golden/make_golden.py rmat20 --ks 3 4 --arcs 5 6 7 8
+    python tests/golden/make_golden.py chunglu22 --ks 3 4 --arcs 5 6 7
 """
 from __future__ import annotations
 
@@ -29,8 +30,14 @@ import oracle  # noqa: E402
 _G = {}
 
 
-def _init(name):
-    g = gg.config_graph(name)
+def _init(name, cache=None):
+    if cache and os.path.exists(cache):
+        # the graph the parent generated (generating it once per worker
+        # would multiply the generator's time and memory)
+        z = np.load(cache)
+        g = gg.CSR(int(z["row_ptr"].shape[0] - 1), z["row_ptr"], z["col"], name)
+    else:
+        g = gg.config_graph(name)
     dptr, dcol = oracle.orient(g.n, g.row_ptr, g.col)
     _G.update(g=g, dptr=dptr, dcol=dcol)
 
@@ -77,14 +84,18 @@ def main():
     if os.path.exists(out_path):
         with open(out_path) as f:
             data = json.load(f)
-    _init(args.name)
+    g0 = gg.config_graph(args.name)
+    cache = os.path.join("/tmp", f"golden_{args.name}_{os.getpid()}.npz")
+    np.savez(cache, row_ptr=g0.row_ptr, col=g0.col)
+    del g0
+    _init(args.name, cache)
     g = _G["g"]
     data.update(graph=args.name, config=gg.CONFIGS[args.name], n=g.n, m=g.m, sha256=g.sha256(),
                 max_outdeg=int(np.diff(_G["dptr"]).max(initial=0)),
                 generator="graphgen (numpy PCG64), numpy " + np.__version__)
     counts = data.setdefault("counts", {})
     P = args.procs
-    with Pool(P, initializer=_init, initargs=(args.name,)) as pool:
+    with Pool(P, initializer=_init, initargs=(args.name, cache)) as pool:
         for k in args.ks:
             t = time.time()
             parts = pool.map(_part, [(k, r, P) for r in range(P)])
@@ -108,6 +119,7 @@ def main():
                       f"total {time.time() - t:.1f} s", flush=True)
                 with open(out_path, "w") as f:
                     json.dump(data, f, indent=1)
+    os.remove(cache)
 
 
 if __name__ == "__main__":

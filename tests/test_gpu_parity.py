@@ -200,6 +200,23 @@ def test_outdegree_one_arcs_read_zero(citron_gpu):
         assert np.array_equal(h.count_arcs(k, np.arange(h.m, dtype=np.int32)), want), k
 
 
+def test_count_parts_add_up(citron_gpu):
+    """Strided shares of the work items add up to the count."""
+    gold = _golden("rmat14")
+    g = gg.config_graph("rmat14")
+    h = load(citron_gpu, g)
+    for k in range(2, 9):
+        want = h.count(k)
+        for nparts in (1, 3, 7):
+            shares = [h.count_part(k, p, nparts)[0] for p in range(nparts)]
+            assert sum(shares) % 2**64 == want, (k, nparts)
+        if str(k) in gold["counts"]:
+            assert want == gold["counts"][str(k)]["count"]
+    for bad in ((0, 0), (3, 3), (-1, 2)):
+        with pytest.raises(citron_gpu.CitronError):
+            h.count_part(5, *bad)
+
+
 _RMAT20 = {}
 
 
@@ -246,6 +263,52 @@ def test_rmat20_sampled_arcs(citron_gpu, k):
         t = time.perf_counter()
         got = h.count_arcs(k, idx[lo:lo + step])
         say(f"rmat20 count_arcs k={k} arcs {lo}..{lo + step - 1}: {time.perf_counter() - t:.2f} s")
+        assert [int(x) for x in got] == want[lo:lo + step], (k, lo)
+
+
+_CL22 = {}
+
+
+def _chunglu22(citron):
+    if "h" not in _CL22:
+        gold = _golden("chunglu22")
+        g = gg.config_graph("chunglu22")
+        assert g.sha256() == gold["sha256"]
+        _CL22.update(g=g, gold=gold, h=load(citron, g))
+    return _CL22["g"], _CL22["gold"], _CL22["h"]
+
+
+def test_chunglu22_counts(citron_gpu):
+    """Full-size Chung-Lu graph (2^22 vertices, 2,000 planted cliques):
+    whole-graph counts against the oracle's."""
+    g, gold, h = _chunglu22(citron_gpu)
+    assert h.info()["max_outdeg"] == gold["max_outdeg"]
+    for k, rec in gold["counts"].items():
+        say("chunglu22 k", k)
+        assert h.count(int(k)) == rec["count"]
+
+
+def test_chunglu22_per_arc_full_launch(citron_gpu):
+    g, gold, h = _chunglu22(citron_gpu)
+    idx = np.array(gold["arcs"]["index"])
+    say("chunglu22 per-arc k 5")
+    total, per_arc = h.count_per_arc(5)
+    assert int(per_arc.sum(dtype=np.uint64)) == total
+    assert [int(x) for x in per_arc[idx]] == gold["arcs"]["5"]
+
+
+@pytest.mark.parametrize("k", [5, 6, 7, 8, 9])
+def test_chunglu22_sampled_arcs(citron_gpu, k):
+    g, gold, h = _chunglu22(citron_gpu)
+    if str(k) not in gold["arcs"]:
+        pytest.skip(f"no stored per-arc values for k = {k}")
+    idx = np.array(gold["arcs"]["index"], dtype=np.int32)
+    want = gold["arcs"][str(k)]
+    step = 32
+    for lo in range(0, len(idx), step):
+        t = time.perf_counter()
+        got = h.count_arcs(k, idx[lo:lo + step])
+        say(f"chunglu22 count_arcs k={k} arcs {lo}..{lo + step - 1}: {time.perf_counter() - t:.2f} s")
         assert [int(x) for x in got] == want[lo:lo + step], (k, lo)
 
 
