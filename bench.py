@@ -253,6 +253,9 @@ def main():
     ap.add_argument("--workload", default="rmat20")
     ap.add_argument("--ks", type=int, nargs="+", default=[5, 6, 7])
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--part-range", type=int, nargs=2, default=None,
+                    help="with --parts: run only shares LO..HI-1 (a long count split over "
+                         "several runs; the line then reports those shares)")
     ap.add_argument("--parts", type=int, default=1,
                     help="run each count as this many strided shares of its work items "
                          "(one launch each, progress after each); for counts of many minutes")
@@ -316,6 +319,8 @@ def main():
     col = torch.from_numpy(g.col).cuda()
     torch.cuda.synchronize()
 
+    shares = {}
+
     def step(record):
         ev = {}
         e0 = torch.cuda.Event(enable_timing=True)
@@ -334,12 +339,19 @@ def main():
                 # the count as strided shares of its work items, one launch
                 # each (progress after each share; the shares add up)
                 tot, ovf = 0, False
-                for p in range(args.parts):
+                lo, hi = args.part_range if args.part_range else (0, args.parts)
+                for p in range(lo, hi):
+                    pa = torch.cuda.Event(enable_timing=True)
+                    pb = torch.cuda.Event(enable_timing=True)
+                    pa.record()
                     v, o = h.count_part(k, p, args.parts)
+                    pb.record()
+                    pb.synchronize()
+                    shares.setdefault(k, []).append({"part": p, "value": v, "overflow": o,
+                                                     "ms": pa.elapsed_time(pb)})
                     tot += v
                     ovf |= o
-                    torch.cuda.synchronize()
-                    log(f"    k={k} share {p + 1}/{args.parts} done")
+                    log(f"    k={k} share {p + 1}/{args.parts}: {v} in {pa.elapsed_time(pb):.1f} ms")
                 counts[k] = (tot % 2**64, ovf or tot >= 2**64)
             else:
                 counts[k] = h.count_checked(k)
@@ -388,13 +400,17 @@ def main():
     # level) per j-clique for j = 3 .. k-1, i.e. sum_{j=3}^{k-1} c_j word
     # operations, each 4 int32 VALU lane-ops.  c_j are exact counts of
     # smaller k, taken from this run or counted outside the timed region.
-    cj = {k: results[k][0] for k in args.ks}
+    # (a partial run of shares does its share of the work)
+    frac_run = 1.0
+    if args.parts > 1 and args.part_range:
+        frac_run = (args.part_range[1] - args.part_range[0]) / args.parts
+    cj = {k: results[k][0] for k in args.ks} if frac_run == 1.0 else {}
     for j in range(3, max(args.ks)):
         if j not in cj:
             cj[j] = h.count(j)
     tot_ops, tot_ms = 0, 0.0
     for k in args.ks:
-        words = sum(cj[j] for j in range(3, k))
+        words = int(sum(cj[j] for j in range(3, k)) * frac_run)
         per_k[str(k)]["alg_word_ops"] = words
         tot_ops += OPS_PER_WORD * words
         tot_ms += per_k[str(k)]["t_count_ms_mean"]
@@ -429,6 +445,11 @@ def main():
         "roofline": roofline,
         "cpu_baseline": cpu,
     }
+    if shares:
+        line["shares"] = {str(k): v for k, v in shares.items()}
+        if args.part_range:
+            # only some shares ran: the counts above are partial sums
+            line["partial"] = {"nparts": args.parts, "range": args.part_range}
     print(json.dumps(line), flush=True)
 
 
