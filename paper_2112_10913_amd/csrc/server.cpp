@@ -9,12 +9,10 @@
 // the next step and share the device with them.  Two lanes keep small
 // requests from waiting behind large ones:
 //   - fast lane (one stream): requests with at most kFastItems items, whole;
-//   - heavy lane (two streams, steps pipelined): the remaining items of the
-//     larger requests in admission order, up to kHeavyStepItems per step,
-//     so that a step works on one or two graphs at a time (their rows stay
-//     in cache) and a long request proceeds in bounded steps between which
-//     fast steps get compute units; while one heavy step drains its last
-//     items the next one takes the freed units.
+//   - heavy lane (two streams): one larger request per step, in admission
+//     order, up to kHeavyStepItems of its items, so that a step works on one
+//     graph (its rows stay in cache); two such steps run at once, and while
+//     one drains its last items the other takes the freed compute units.
 // Steps of a lane retire in issue order; a request whose items have all
 // retired returns its count and frees its slot.  Counts are exact integers,
 // so a request's count does not depend on which requests it shares steps
@@ -60,7 +58,7 @@ struct Req {
 // steps of at most kItemsPerStep items, kItemsPerReq per request.
 constexpr int32_t kFastItems = 4096;
 constexpr int32_t kFastStepItems = 65536;
-constexpr int32_t kHeavyStepItems = 65536;
+constexpr int32_t kHeavyStepItems = 1 << 20;
 constexpr int kInflight = 3;              // step 0: fast lane; 1, 2: heavy lane
 
 // One step's launch resources (reused once the step has retired).
@@ -155,7 +153,7 @@ bool issue_step(citron_server* s, Step& st, bool fast, int wg, int32_t blocks)
         if (total >= cap) break;
         int32_t take = r.n_items - r.issued;
         if (fast && total + take > cap && total > 0) break;
-        if (!fast) take = std::min(take, cap - total);
+        if (!fast) take = std::min(take, cap);
         QueryDesc q = r.q;
         q.item_begin = total;
         q.item_lo = r.issued;
@@ -165,6 +163,7 @@ bool issue_step(citron_server* s, Step& st, bool fast, int wg, int32_t blocks)
         r.issued += take;
         total += take;
         maxk = std::max(maxk, r.k);
+        if (!fast) break;            // one request per heavy step
     }
     hipError_t e = launch_fill_i32(st.d_item_ctr, 0, 1, st.stream);
     if (e == hipSuccess)
