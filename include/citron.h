@@ -209,8 +209,11 @@ citron_status citron_device_info(int32_t* cus, int32_t* lds_bytes, char* name64)
 
 /* A request loop over resident graphs with continuous batching: requests
  * that arrive while others run are admitted as soon as a slot and device
- * memory are free, and share the running persistent kernel.  One server
- * drives one device from one host thread of its own. */
+ * memory are free, and their work overlaps on the device with the work
+ * already running.  Small requests (few work items) are batched whole into
+ * steps of a fast lane; each larger request runs as steps of its own, two
+ * at a time on two streams.  Results do not depend on the mix a request is
+ * served in.  One server drives one device from one host thread of its own. */
 typedef struct {
     uint64_t tag;        /* the caller's tag from citron_server_submit */
     int32_t graph_id;
