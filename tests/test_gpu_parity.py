@@ -92,6 +92,29 @@ def test_closed_forms(citron_gpu):
             assert h.count(k) == want(k), (g.name, k)
 
 
+def test_large_k_stack_modes(citron_gpu):
+    """k above 8 keeps the search stacks in LDS (k <= 12) or in device
+    memory (k >= 13): closed forms and the oracle at those k, plain and
+    per-arc launches."""
+    cases = [
+        (gg.complete(32), lambda k: math.comb(32, k), range(9, 21)),
+        (gg.complete(66), lambda k: math.comb(66, k), range(9, 11)),   # two-word rows
+        (gg.turan(36, 12), lambda k: _esym([3] * 12, k), range(9, 14)),
+    ]
+    for g, want, ks in cases:
+        h = load(citron_gpu, g)
+        for k in ks:
+            say("large k", g.name, k)
+            assert h.count(k) == want(k), (g.name, k)
+            total, per_arc = h.count_per_arc(k)
+            assert total == want(k) and int(per_arc.sum(dtype=np.uint64)) == total, (g.name, k)
+    g = gg.erdos_renyi(120, 0.6 * 119, seed=12)
+    h = load(citron_gpu, g)
+    for k in range(9, 15):
+        say("large k ER", k)
+        assert h.count(k) == ocount(g, k), k
+
+
 def test_random_fuzz(citron_gpu):
     rng = np.random.default_rng(2112)
     for i in range(40):
