@@ -17,15 +17,18 @@
 // Engines.  Light work -- subgraphs with at most 64 vertices, one 64-bit
 // word per row -- is searched by the light engine: one depth-first search
 // per lane over one first-level branch at a time, rows in the wave's LDS
-// buffer.  A heavy arc is walked by the whole wave in step (lane q holding
-// word q of each mask, rows read from device memory) until a node has at
-// most 64 candidates; that node's induced subgraph is then compacted to one
-// word per row and queued in the wave's LDS buffer for the light engine.
+// buffer, stacks in registers (k <= 8), LDS (k <= 12) or device memory.
+// A heavy arc is walked by the whole wave in step (lane q holding word q of
+// each mask).  A node with at most 256 candidates is copied to the wave's
+// LDS, compacted to ceil(c/64) words per row; a node with at most 64
+// candidates is compacted to one word per row and queued for the light
+// engine; a node with two levels left and more than 64 candidates is
+// finished lane-per-child from the LDS copy (need3_lanes).
 //
 // Exact arithmetic: per-lane uint64 accumulators (a lane adds at most 64 per
-// step and cannot run 2^58 steps, so these never wrap); wave sums and the
-// global accumulator are carry-checked, and a carry sets the query's
-// overflow flag.
+// step and cannot run 2^58 steps, so these never wrap; 32-bit partial sums
+// are bounded where they are used); wave sums and the global accumulator
+// are carry-checked, and a carry sets the query's overflow flag.
 #include "kernels.h"
 
 namespace citron {
