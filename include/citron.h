@@ -74,7 +74,14 @@ typedef struct {
                                 searches them: 64..256 */
     int32_t build_blocks_per_cu; /* persistent build workgroups per compute
                                 unit: 1..16 */
-    int32_t reserved;        /* must be 0 */
+    int32_t split_pct;       /* scale of the number of parts a heavy arc or a
+                                light vertex is split into, percent: 25..400
+                                (schedule of a graph's counts; set it on the
+                                graph, a batch uses each graph's own) */
+    int32_t arc_lds_max;     /* subgraph representation switch: nodes with at
+                                most this many candidates (and more than 64)
+                                are copied to LDS, larger ones are walked in
+                                device memory: 64..256 */
 } citron_tuning;
 
 /* ------------------------------------------------------------- graphs */
@@ -158,7 +165,10 @@ citron_status citron_get_dag(const citron_graph* g, int32_t* dag_ptr, int32_t* d
 citron_status citron_graph_info(const citron_graph* g, int64_t* n, int64_t* m,
                                 int32_t* max_outdeg, int64_t* device_bytes);
 
-/* Per-graph tuning (copied).  NULL restores the defaults. */
+/* Per-graph tuning (copied).  NULL restores the defaults.  Zero fields
+ * take their defaults (wg_waves 4, blocks_per_cu 2, light_rows 256,
+ * flush_rows 128, build_blocks_per_cu 4, split_pct 100, arc_lds_max 256).
+ * Not to be changed while the graph is registered with a server. */
 citron_status citron_set_tuning(citron_graph* g, const citron_tuning* t);
 citron_status citron_get_tuning(const citron_graph* g, citron_tuning* t);
 

@@ -41,7 +41,7 @@ class _Tuning(ctypes.Structure):
     _fields_ = [("size", ctypes.c_int32), ("wg_waves", ctypes.c_int32),
                 ("blocks_per_cu", ctypes.c_int32), ("light_rows", ctypes.c_int32),
                 ("flush_rows", ctypes.c_int32), ("build_blocks_per_cu", ctypes.c_int32),
-                ("reserved", ctypes.c_int32)]
+                ("split_pct", ctypes.c_int32), ("arc_lds_max", ctypes.c_int32)]
 
 
 @dataclass
@@ -53,7 +53,8 @@ class Tuning:
     light_rows: int = 0
     flush_rows: int = 0
     build_blocks_per_cu: int = 0
-    reserved: int = 0
+    split_pct: int = 0
+    arc_lds_max: int = 0
 
     def _c(self) -> _Tuning:
         t = _Tuning()

@@ -33,7 +33,8 @@ citron_tuning default_tuning()
     t.light_rows = 256;
     t.flush_rows = 128;
     t.build_blocks_per_cu = 4;
-    t.reserved = 0;
+    t.split_pct = 100;
+    t.arc_lds_max = 256;
     return t;
 }
 
@@ -49,6 +50,8 @@ citron_status resolve_tuning(const citron_tuning* in, citron_tuning* out)
     if (t.light_rows == 0) t.light_rows = d.light_rows;
     if (t.flush_rows == 0) t.flush_rows = d.flush_rows;
     if (t.build_blocks_per_cu == 0) t.build_blocks_per_cu = d.build_blocks_per_cu;
+    if (t.split_pct == 0) t.split_pct = d.split_pct;
+    if (t.arc_lds_max == 0) t.arc_lds_max = d.arc_lds_max;
     if (t.wg_waves < 1 || t.wg_waves > 8) return fail(CITRON_EINVAL, "wg_waves must be in 1..8");
     if (t.blocks_per_cu < 1 || t.blocks_per_cu > 32) return fail(CITRON_EINVAL, "blocks_per_cu must be in 1..32");
     if (t.light_rows < 64 || t.light_rows > 1024 || t.light_rows % 64)
@@ -56,7 +59,9 @@ citron_status resolve_tuning(const citron_tuning* in, citron_tuning* out)
     if (t.flush_rows < 64 || t.flush_rows > 256) return fail(CITRON_EINVAL, "flush_rows must be in 64..256");
     if (t.build_blocks_per_cu < 1 || t.build_blocks_per_cu > 16)
         return fail(CITRON_EINVAL, "build_blocks_per_cu must be in 1..16");
-    if (t.reserved != 0) return fail(CITRON_EINVAL, "citron_tuning.reserved must be 0");
+    if (t.split_pct < 25 || t.split_pct > 400) return fail(CITRON_EINVAL, "split_pct must be in 25..400");
+    if (t.arc_lds_max < 64 || t.arc_lds_max > kArcLdsMax)
+        return fail(CITRON_EINVAL, "arc_lds_max must be in 64..256");
     *out = t;
     return CITRON_OK;
 }
@@ -268,7 +273,10 @@ citron_status ensure_scratch(citron_graph* g, int64_t bytes)
 // first.  Arcs and vertices are split into parts (arc_parts, light_parts).
 citron_status ensure_buckets(citron_graph* g, int32_t k)
 {
-    if (g->d_buckets[k]) return CITRON_OK;
+    const int32_t pct = g->tuning.split_pct;
+    if (g->d_buckets[k] && g->bucket_split[k] == pct) return CITRON_OK;
+    dfree(g->d_buckets[k]);
+    g->d_buckets[k] = nullptr;
     const int32_t D = std::max(g->max_outdeg, 2);
     auto v_at_least = [&](int32_t x) -> int64_t {   // vertices with out-degree >= x
         if (x > D) return 0;
@@ -296,7 +304,7 @@ citron_status ensure_buckets(citron_graph* g, int32_t k)
     while (ih < hb.size() || il < lb.size()) {
         const bool take_h = il >= lb.size() || (ih < hb.size() && hb[ih].key >= lb[il].key);
         const B b = take_h ? hb[ih++] : lb[il++];
-        const int32_t parts = b.light ? light_parts(b.key + 1, k) : arc_parts(b.key, k);
+        const int32_t parts = b.light ? light_parts(b.key + 1, k, pct) : arc_parts(b.key, k, pct);
         tab.push_back((int32_t)items);
         tab.push_back(b.first);
         tab.push_back(b.cnt);
@@ -315,6 +323,7 @@ citron_status ensure_buckets(citron_graph* g, int32_t k)
     if (e != hipSuccess) return hip_fail(e, "item buckets");
     g->n_buckets[k] = nb;
     g->n_work[k] = (int32_t)items;
+    g->bucket_split[k] = pct;
     return CITRON_OK;
 }
 
@@ -342,6 +351,7 @@ QueryDesc make_query(const citron_graph* g, int32_t k, unsigned long long* acc, 
     q.item_begin = item_begin;
     q.n_items = q.n_work;
     q.item_stride = 1;
+    q.split_pct = g->bucket_split[k];
     return q;
 }
 
@@ -381,7 +391,8 @@ struct ListItems {
             hipMalloc((void**)&offs, sizeof(int32_t) * ((size_t)n + 1)) != hipSuccess ||
             hipMalloc((void**)&ws, sizeof(int32_t) * scan_workspace_ints(n)) != hipSuccess)
             return fail(CITRON_ENOMEM, "hipMalloc failed for the arc list");
-        hipError_t e = launch_list_parts(arcs, n, g->d_dag_src, g->d_dag_ptr, g->d_arc_c, k, parts, s);
+        hipError_t e = launch_list_parts(arcs, n, g->d_dag_src, g->d_dag_ptr, g->d_arc_c, k, g->tuning.split_pct,
+                                         parts, s);
         if (e == hipSuccess) e = scan_exclusive(parts, offs, n, ws, s);
         if (e == hipSuccess) e = hipMemcpyAsync(&g->h_small->ends[0], offs + n, sizeof(int32_t),
                                                 hipMemcpyDeviceToHost, s);
@@ -490,6 +501,7 @@ static citron_status run_single(citron_graph* g, int32_t k, unsigned long long* 
     cl.wg_waves = wg;
     cl.lds_bytes = count_lds_bytes(0, k, wg);
     cl.flush_rows = t.flush_rows;
+    cl.arc_lds_max = t.arc_lds_max;
     cl.stats = stats;
     cl.per_arc = per_arc != nullptr;
     e = launch_count(cl, s);
@@ -787,6 +799,8 @@ citron_status citron_set_tuning(citron_graph* g, const citron_tuning* t)
     citron_tuning r;
     citron_status st = resolve_tuning(t, &r);
     if (st) return st;
+    const bool resplit = r.split_pct != g->tuning.split_pct;
+    if (resplit) batch_forget_graph(g);   // captured batches hold its schedule
     std::lock_guard<std::mutex> lock(g->mu);
     g->tuning = r;
     return CITRON_OK;

@@ -95,6 +95,7 @@ struct citron_graph {
     bool tri_ovf = false;
     // per k: the merged bucket table of the count's work items
     int32_t* d_buckets[CITRON_KMAX + 1] = {};
+    int32_t bucket_split[CITRON_KMAX + 1] = {};   // split_pct each table was built with
     int32_t n_buckets[CITRON_KMAX + 1] = {};
     int32_t n_work[CITRON_KMAX + 1] = {};
     uint64_t build_stats[citron::kNumStats] = {};

@@ -20,7 +20,7 @@ namespace {
 struct BatchKey {
     std::vector<const citron_graph*> graphs;
     std::vector<int32_t> ks;
-    int32_t tuning[7];
+    int32_t tuning[sizeof(citron_tuning) / sizeof(int32_t)];
     bool operator<(const BatchKey& o) const
     {
         if (graphs != o.graphs) return graphs < o.graphs;
@@ -132,6 +132,7 @@ citron_status batch_build(const BatchKey& key, const citron_tuning& t, BatchExec
     cl.wg_waves = wg;
     cl.lds_bytes = count_lds_bytes(0, max_k, wg);
     cl.flush_rows = t.flush_rows;
+    cl.arc_lds_max = t.arc_lds_max;
     cl.stats = false;
     cl.per_arc = false;
 
@@ -193,8 +194,7 @@ extern "C" citron_status citron_count_batch(citron_graph* const* gs, const int32
         }
     }
     if (!key.ks.empty()) {
-        memcpy(key.tuning, &t.wg_waves, sizeof(key.tuning) - sizeof(int32_t));
-        key.tuning[6] = 0;
+        memcpy(key.tuning, &t, sizeof(key.tuning));
         std::lock_guard<std::mutex> lock(g_batch_mu);
         hipError_t e = hipSetDevice(dev);
         if (e != hipSuccess) return hip_fail(e, "hipSetDevice");

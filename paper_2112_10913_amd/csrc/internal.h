@@ -12,6 +12,7 @@ constexpr int kLightMaxDeg = 64;     // out-degree that fits one 64-bit row word
 constexpr int kMaxWords = 64;        // row words per subgraph (out-degree <= 4096)
 constexpr int kMaxDeg = kMaxWords * 64;
 constexpr int kKMax = 32;
+constexpr int kArcLdsMax = 256;      // largest candidate set an LDS subgraph copy holds
 
 // Count-kernel statistics slots (citron_work_stats).
 enum StatSlot {
@@ -101,6 +102,8 @@ struct QueryDesc {
     int32_t n_items;             // items of this query in the launch
     int32_t item_lo;             // local index of the query's first item in the launch
     int32_t item_stride;         // local item of launch item g: item_lo + (g - item_begin) * item_stride
+    int32_t split_pct;           // split scale the buckets were built with (arc_parts, light_parts)
+    int32_t pad;
     // list mode (arc_list != nullptr): item j is (slot, part) = (arc_items[2j],
     // arc_items[2j+1] & 0xffff) of arc arc_list[slot], split into
     // arc_items[2j+1] >> 16 parts; its counts go to per-arc slot `slot`
@@ -109,21 +112,30 @@ struct QueryDesc {
 };
 
 // Parts a heavy arc with |C_uv| = c is split into for a k-clique count; each
-// part takes every P-th first-level branch of the arc (speed only).
-__host__ __device__ inline int arc_parts(int c, int k)
+// part takes every P-th first-level branch of the arc (speed only).  pct
+// scales the default (percent); arcs are split only for k >= 6, where the
+// root of an arc has at least four levels left.
+__host__ __device__ inline int scale_parts(int base, int pct)
+{
+    if (base <= 1) return 1;
+    const int p = base * pct / 100;
+    return p < 1 ? 1 : (p > 64 ? 64 : p);
+}
+
+__host__ __device__ inline int arc_parts(int c, int k, int pct)
 {
     if (k <= 5) return 1;
-    if (k == 6) return c < 64 ? 1 : (c / 32 < 8 ? c / 32 : 8);
-    return c < 16 ? 1 : (c / 8 < 32 ? c / 8 : 32);
+    if (k == 6) return scale_parts(c < 64 ? 1 : (c / 32 < 8 ? c / 32 : 8), pct);
+    return scale_parts(c < 16 ? 1 : (c / 8 < 32 ? c / 8 : 32), pct);
 }
 
 // Parts a light vertex (out-degree d <= 64, its subgraph one word per row)
 // is split into; each part takes every P-th arc of the vertex (speed only).
-__host__ __device__ inline int light_parts(int d, int k)
+__host__ __device__ inline int light_parts(int d, int k, int pct)
 {
     if (k <= 5) return 1;
-    if (k == 6) return d >= 32 ? d / 8 : 1;
-    return d >= 12 ? d / 2 : 1;
+    if (k == 6) return scale_parts(d >= 32 ? d / 8 : 1, pct);
+    return scale_parts(d >= 12 ? d / 2 : 1, pct);
 }
 
 }  // namespace citron

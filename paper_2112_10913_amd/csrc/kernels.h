@@ -68,6 +68,7 @@ struct CountLaunch {
     int32_t wg_waves;
     int32_t lds_bytes;          // dynamic LDS per block
     int32_t flush_rows;
+    int32_t arc_lds_max = 256;  // heavy nodes with 64 < c <= this are copied to LDS
     bool stats;                 // instrumented launch
     bool per_arc;               // some query writes per-arc counts
 };
@@ -76,7 +77,7 @@ int32_t count_lds_bytes(int32_t light_rows, int32_t max_k, int32_t wg_waves);
 hipError_t launch_count(const CountLaunch& cl, hipStream_t s);
 hipError_t launch_check_arcs(const int32_t* arcs, int32_t n, int64_t m, int32_t* err, hipStream_t s);
 hipError_t launch_list_parts(const int32_t* arcs, int32_t n, const int32_t* dag_src, const int32_t* dag_ptr,
-                             const int32_t* arc_c, int32_t k, int32_t* parts, hipStream_t s);
+                             const int32_t* arc_c, int32_t k, int32_t pct, int32_t* parts, hipStream_t s);
 hipError_t launch_list_items(int32_t n, const int32_t* parts, const int32_t* offs, int32_t* items, hipStream_t s);
 hipError_t launch_gather_arc_c(const int32_t* arcs, int32_t n, const int32_t* arc_c, unsigned long long* out,
                                hipStream_t s);

@@ -38,7 +38,7 @@ typedef unsigned long long u64;
 constexpr int kMaxBlock = 512;          // threads per count workgroup (8 waves)
 constexpr int kWaveBufRows = 256;       // one-word rows queued per wave
 constexpr int kLdsStackLevels = 8;      // deeper stacks (k > 12) live in device memory
-constexpr int kArcMaxC = 256;           // heavy arcs with |C_uv| <= this are copied to LDS
+constexpr int kArcMaxC = kArcLdsMax;    // LDS subgraph copies hold at most this many rows
 constexpr int kArcWords = kArcMaxC * (kArcMaxC / 64);   // 8 KB per wave
 constexpr int kLaneMaxWords = 4;        // multi-word masks a lane holds in registers
 constexpr int kDonateMinIdle = 8;       // idle lanes that trigger work donation
@@ -217,6 +217,7 @@ struct WaveBuf {
     int32_t* units;  // rows that are search roots (a part of a split arc uses some rows only)
     int n;           // rows in use (wave-uniform)
     int nu;          // units in use (wave-uniform)
+    int arc_max;     // nodes with 64 < c <= arc_max are copied to LDS
 };
 
 // Per-lane light stack: slot s holds the (M, R) pair of level s + 1.  In
@@ -721,7 +722,7 @@ __device__ __forceinline__ bool heavy_node(const HeavyCtx<kGlobal>& H, u64 m, in
         return false;
     }
     if constexpr (kGlobal) {
-    if (c <= kArcMaxC && c > kWave) {
+    if (c <= wb.arc_max && c > kWave) {
         // continue from an LDS copy of this node's subgraph
         const u64 c0 = kStats ? __builtin_readcyclecounter() : 0ull;
         lds_u64* arc = (lds_u64*)wb.arc;
@@ -742,7 +743,7 @@ __device__ __forceinline__ bool heavy_node(const HeavyCtx<kGlobal>& H, u64 m, in
         const u64 c0 = kStats ? __builtin_readcyclecounter() : 0ull;
         const int nj = (c - part + P - 1) / P;
         // positions of the candidates taken, in the mailbox area (idle while
-        // the light engine is not running); nj <= c <= kArcMaxC <= kPosList
+        // the light engine is not running); nj <= c <= arc_max <= kArcMaxC <= kPosList
         lds_i32* pos = (lds_i32*)wb.mbox;
         for (int j0 = 0; j0 < nj; j0 += kWave) {
             const int jj = j0 + lane;
@@ -870,6 +871,7 @@ struct KParams {
     int64_t scratch_words;
     int32_t max_k;
     int32_t flush_rows;     // a wave runs its queue once it holds this many rows
+    int32_t arc_lds_max;    // representation switch of heavy nodes (64..kArcMaxC)
 };
 
 template <int kMode, bool kStats, bool kPerArc>
@@ -908,6 +910,7 @@ __global__ void __launch_bounds__(kMaxBlock) count_kernel(KParams P)
     }
     wb.n = 0;
     wb.nu = 0;
+    wb.arc_max = P.arc_lds_max;
 
     Acc A;
     A.acc = 0ull;
@@ -988,11 +991,11 @@ __global__ void __launch_bounds__(kMaxBlock) count_kernel(KParams P)
                 const int e = q.rows.harcs[which];
                 u = q.dag_src[e];
                 r = e - q.dag_ptr[u];
-                nparts = arc_parts(key, k);
+                nparts = arc_parts(key, k, q.split_pct);
                 tag = e;
             } else {
                 u = q.order[q.light_first + which];
-                nparts = light_parts(key + 1, k);
+                nparts = light_parts(key + 1, k, q.split_pct);
                 tag = -1;
             }
         }
@@ -1081,6 +1084,7 @@ hipError_t launch_count(const CountLaunch& cl, hipStream_t s)
     P.scratch_words = cl.scratch_words;
     P.max_k = cl.max_k;
     P.flush_rows = cl.flush_rows;
+    P.arc_lds_max = cl.arc_lds_max < kWave ? kWave : (cl.arc_lds_max > kArcMaxC ? kArcMaxC : cl.arc_lds_max);
     switch (stack_mode(cl.max_k)) {
     case kStackReg: return launch_mode<kStackReg>(P, cl, s);
     case kStackLds: return launch_mode<kStackLds>(P, cl, s);
@@ -1181,14 +1185,14 @@ __global__ void gather_arc_c_kernel(const int32_t* __restrict__ arcs, int32_t n,
 // parts of each listed arc (heavy sources split as in the full schedule)
 __global__ void list_parts_kernel(const int32_t* __restrict__ arcs, int32_t n, const int32_t* __restrict__ dag_src,
                                   const int32_t* __restrict__ dag_ptr, const int32_t* __restrict__ arc_c, int32_t k,
-                                  int32_t* __restrict__ parts)
+                                  int32_t pct, int32_t* __restrict__ parts)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     const int e = arcs[i];
     const int u = dag_src[e];
     const int d = dag_ptr[u + 1] - dag_ptr[u];
-    parts[i] = d > kLightMaxDeg ? arc_parts(arc_c[e], k) : 1;
+    parts[i] = d > kLightMaxDeg ? arc_parts(arc_c[e], k, pct) : 1;
 }
 
 __global__ void list_items_kernel(int32_t n, const int32_t* __restrict__ parts, const int32_t* __restrict__ offs,
@@ -1205,10 +1209,10 @@ __global__ void list_items_kernel(int32_t n, const int32_t* __restrict__ parts, 
 }
 
 hipError_t launch_list_parts(const int32_t* arcs, int32_t n, const int32_t* dag_src, const int32_t* dag_ptr,
-                             const int32_t* arc_c, int32_t k, int32_t* parts, hipStream_t s)
+                             const int32_t* arc_c, int32_t k, int32_t pct, int32_t* parts, hipStream_t s)
 {
     if (n <= 0) return hipSuccess;
-    list_parts_kernel<<<(n + 255) / 256, 256, 0, s>>>(arcs, n, dag_src, dag_ptr, arc_c, k, parts);
+    list_parts_kernel<<<(n + 255) / 256, 256, 0, s>>>(arcs, n, dag_src, dag_ptr, arc_c, k, pct, parts);
     return hipGetLastError();
 }
 

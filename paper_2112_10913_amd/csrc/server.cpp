@@ -181,6 +181,7 @@ bool issue_step(citron_server* s, Step& st, bool fast, int wg, int32_t blocks)
         cl.wg_waves = wg;
         cl.lds_bytes = count_lds_bytes(0, maxk, wg);
         cl.flush_rows = s->tuning.flush_rows;
+        cl.arc_lds_max = s->tuning.arc_lds_max;
         cl.stats = false;
         cl.per_arc = false;
         e = launch_count(cl, st.stream);

@@ -39,10 +39,11 @@ def test_query_subsets_and_order(citron_gpu, queries):
 def test_autotune_keeps_counts(citron_gpu, queries, tmp_path):
     from paper_2112_10913_amd.autotune import autotune
     gs, ks, plain = queries
-    space = {"wg_waves": [2, 4], "blocks_per_cu": [1, 2], "flush_rows": [64, 128]}
+    space = {"wg_waves": [2, 4], "blocks_per_cu": [1, 2], "flush_rows": [64, 128], "arc_lds_max": [128, 256],
+             "split_pct": [50, 200]}
     cache = str(tmp_path / "tune.json")
     best, report = autotune(gs, ks, space=space, reps=1, cache_path=cache)
-    assert not report["cached"] and len(report["trials"]) == 8
+    assert not report["cached"] and len(report["trials"]) == 32
     assert citron_gpu.count_batch(gs, ks, tuning=best) == plain
     again, rep2 = autotune(gs, ks, space=space, reps=1, cache_path=cache)
     assert rep2["cached"] and again == best

@@ -341,14 +341,23 @@ def test_tuning_invariance(citron_gpu):
     gold = _golden("rmat14")
     g = gg.config_graph("rmat14")
     want = {k: gold["counts"][str(k)]["count"] for k in (3, 4, 5, 6)}
+    idx = np.array(gold["arcs"]["index"])
+    deep = {}
     for tu in [dict(wg_waves=1, blocks_per_cu=1, light_rows=64, flush_rows=64, build_blocks_per_cu=1),
                dict(wg_waves=8, blocks_per_cu=1, light_rows=1024, flush_rows=256, build_blocks_per_cu=16),
-               dict(wg_waves=2, blocks_per_cu=8, light_rows=128, flush_rows=100, build_blocks_per_cu=2)]:
+               dict(wg_waves=2, blocks_per_cu=8, light_rows=128, flush_rows=100, build_blocks_per_cu=2),
+               dict(split_pct=25, arc_lds_max=64), dict(split_pct=400, arc_lds_max=128),
+               dict(split_pct=250, arc_lds_max=192)]:
         h = citron_gpu.Graph.from_csr(g.row_ptr, g.col)
         h.set_tuning(citron_gpu.Tuning(**tu))   # before the first count: shapes the build too
         h.order()
         for k, w in want.items():
             assert h.count(k) == w, (tu, k)
+        for k in (7, 8):    # split factors matter most here
+            total, per_arc = h.count_per_arc(k)
+            assert [int(x) for x in per_arc[idx]] == gold["arcs"][str(k)], (tu, k)
+            deep.setdefault(k, set()).add(total)
+    assert all(len(v) == 1 for v in deep.values()), deep
 
 
 def test_relabel_invariance_gpu(citron_gpu):
