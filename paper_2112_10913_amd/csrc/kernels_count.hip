@@ -44,7 +44,7 @@ constexpr int kLaneMaxWords = 4;        // multi-word masks a lane holds in regi
 constexpr int kDonateMinIdle = 8;       // idle lanes that trigger work donation
 constexpr int kBurstIters = 32;         // last-level steps of one leaf burst at most
 constexpr int kBurstMinLanes = 32;      // lanes at a last-level node to keep a burst going
-constexpr int kN3Burst = 4;             // two-level steps between refills of idle lanes
+constexpr int kN3Burst = 8;             // two-level steps between refills of idle lanes
 constexpr int kPosList = 512;           // candidate positions the mailbox area holds (2 KB)
 static_assert(kArcMaxC <= kPosList, "candidate positions of an LDS node fit the mailbox area");
 
