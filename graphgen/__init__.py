@@ -23,6 +23,8 @@ from __future__ import annotations
 import hashlib
 from dataclasses import dataclass, field
 
+from itertools import combinations
+
 import numpy as np
 
 __all__ = [
@@ -305,6 +307,26 @@ def disjoint_cliques(sizes) -> CSR:
     s = np.concatenate(s_all) if s_all else np.zeros(0, np.int64)
     d = np.concatenate(d_all) if d_all else np.zeros(0, np.int64)
     return csr_from_edges(off, s, d, name="cliques" + "+".join(map(str, sizes)))
+
+
+def paley(q: int) -> CSR:
+    """Paley graph of a prime q = 1 mod 4: x ~ y iff x - y is a nonzero square mod q."""
+    if q < 5 or q % 4 != 1 or any(q % p == 0 for p in range(2, int(q ** 0.5) + 1)):
+        raise ValueError("q must be a prime congruent to 1 mod 4")
+    squares = np.zeros(q, bool)
+    squares[(np.arange(1, q) ** 2) % q] = True
+    iu, ju = np.triu_indices(q, 1)
+    keep = squares[(ju - iu) % q]
+    return csr_from_edges(q, iu[keep], ju[keep], name=f"Paley{q}")
+
+
+def kneser(n: int, r: int) -> CSR:
+    """Kneser graph K(n, r): the r-subsets of {0..n-1}, adjacent iff disjoint."""
+    subsets = list(combinations(range(n), r))
+    masks = np.array([sum(1 << e for e in s) for s in subsets], dtype=np.int64)
+    iu, ju = np.triu_indices(len(subsets), 1)
+    keep = (masks[iu] & masks[ju]) == 0
+    return csr_from_edges(len(subsets), iu[keep], ju[keep], name=f"Kneser({n},{r})")
 
 
 def empty(n: int) -> CSR:

@@ -4,7 +4,7 @@ and by mathematics, never against the oracle itself:
 * the worked example of Fig. 1 (DAG, induced subgraph, counts, per arc);
 * brute-force subset enumeration on random small graphs (definition);
 * closed forms: complete, Turan, bipartite, grid, hypercube, wheel,
-  disjoint cliques, empty graphs;
+  disjoint cliques, Paley (strongly regular), Kneser, empty graphs;
 * triangles = trace(A^3)/6 computed by scipy sparse matrix products;
 * invariance of every count under vertex relabelling;
 * per-size visit counts equal to the counts at smaller k;
@@ -171,6 +171,43 @@ def test_disjoint_cliques():
     g = gg.disjoint_cliques(sizes)
     for k in range(1, 10):
         assert ocount(g, k) == sum(math.comb(s, k) for s in sizes)
+
+
+@pytest.mark.parametrize("q", [5, 13, 17, 29, 37, 101])
+def test_paley_triangles(q):
+    # Paley graphs are strongly regular with degree (q-1)/2 and (q-5)/4 common
+    # neighbours per edge: m = q(q-1)/4 and q(q-1)(q-5)/48 triangles
+    g = gg.paley(q)
+    assert ocount(g, 2) == q * (q - 1) // 4
+    assert ocount(g, 3) == q * (q - 1) * (q - 5) // 48
+
+
+def test_paley17_has_no_k4():
+    # the Paley graph on 17 vertices shows R(4,4) > 17: no 4-clique (and,
+    # being self-complementary, no independent 4-set)
+    g = gg.paley(17)
+    assert ocount(g, 3) == 68 and ocount(g, 4) == 0
+
+
+def _kneser_cliques(n, r, k):
+    # a k-clique is an unordered choice of k pairwise disjoint r-subsets
+    if r * k > n:
+        return 0
+    return math.factorial(n) // (math.factorial(r) ** k * math.factorial(k) * math.factorial(n - r * k))
+
+
+@pytest.mark.parametrize("n,r", [(5, 2), (7, 2), (8, 2), (10, 2), (9, 3), (11, 3)])
+def test_kneser(n, r):
+    g = gg.kneser(n, r)
+    assert g.n == math.comb(n, r)
+    for k in range(1, n // r + 2):
+        assert ocount(g, k) == _kneser_cliques(n, r, k), k
+
+
+def test_petersen():
+    g = gg.kneser(5, 2)
+    assert (g.n, g.m) == (10, 15)
+    assert [ocount(g, k) for k in (3, 4)] == [0, 0]
 
 
 def test_empty():
