@@ -4,6 +4,7 @@
 #include "api_internal.h"
 
 #include <algorithm>
+#include <atomic>
 #include <cstring>
 #include <string>
 
@@ -68,12 +69,15 @@ citron_status resolve_tuning(const citron_tuning* in, citron_tuning* out)
 
 int device_cus(int dev)
 {
-    static int cached[64] = {0};
-    if (dev >= 0 && dev < 64 && cached[dev]) return cached[dev];
+    static std::atomic<int> cached[64];   // zero-initialised (static storage)
+    if (dev >= 0 && dev < 64) {
+        const int c = cached[dev].load(std::memory_order_relaxed);
+        if (c) return c;
+    }
     int cus = 0;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
         cus = 256;
-    if (dev >= 0 && dev < 64) cached[dev] = cus;
+    if (dev >= 0 && dev < 64) cached[dev].store(cus, std::memory_order_relaxed);
     return cus;
 }
 
@@ -130,7 +134,10 @@ static void free_graph_memory(citron_graph* g)
     dfree(g->d_hhist);
     dfree(g->d_hscan);
     dfree(g->d_hcur);
-    for (int k = 0; k <= CITRON_KMAX; ++k) dfree(g->d_buckets[k]);
+    for (int k = 0; k <= CITRON_KMAX; ++k) {
+        dfree(g->d_buckets[k]);
+        g->bucket_bytes[k] = 0;
+    }
     g->rows_valid = false;
     free_plan(g);
     if (g->h_small) (void)hipHostFree(g->h_small);
@@ -145,16 +152,18 @@ citron_status ensure_plan(citron_graph* g, const citron_tuning& t)
     hipError_t e = hipSetDevice(g->device);
     if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
     const int32_t D = std::max(g->max_outdeg, 2);
-    if (!g->pb.order) {
+    {
+        // each buffer is allocated once; a call that failed part-way keeps
+        // what it allocated and a retry allocates only the rest
         int64_t* acct = &g->device_bytes;
         citron_status st;
-        if ((st = dalloc(&g->pb.hist, (size_t)D + 2, acct, "plan")) ||
-            (st = dalloc(&g->pb.hist_scan, (size_t)D + 3, acct, "plan")) ||
-            (st = dalloc(&g->pb.order, (size_t)g->n + 1, acct, "plan")) ||
-            (st = dalloc(&g->pb.light_deg, (size_t)g->n + 1, acct, "plan")) ||
-            (st = dalloc(&g->pb.light_pre, (size_t)g->n + 2, acct, "plan")) ||
-            (st = dalloc(&g->pb.batch_start, (size_t)g->n + 2, acct, "plan")) ||
-            (st = dalloc(&g->pb.header, 1, acct, "plan")))
+        if ((!g->pb.hist && (st = dalloc(&g->pb.hist, (size_t)D + 2, acct, "plan"))) ||
+            (!g->pb.hist_scan && (st = dalloc(&g->pb.hist_scan, (size_t)D + 3, acct, "plan"))) ||
+            (!g->pb.order && (st = dalloc(&g->pb.order, (size_t)g->n + 1, acct, "plan"))) ||
+            (!g->pb.light_deg && (st = dalloc(&g->pb.light_deg, (size_t)g->n + 1, acct, "plan"))) ||
+            (!g->pb.light_pre && (st = dalloc(&g->pb.light_pre, (size_t)g->n + 2, acct, "plan"))) ||
+            (!g->pb.batch_start && (st = dalloc(&g->pb.batch_start, (size_t)g->n + 2, acct, "plan"))) ||
+            (!g->pb.header && (st = dalloc(&g->pb.header, 1, acct, "plan"))))
             return st;
     }
     e = launch_plan(g->n, g->d_dag_ptr, g->max_outdeg, t.light_rows, 0, 1, g->pb, g->d_scan_ws, g->stream);
@@ -186,15 +195,13 @@ citron_status ensure_rows(citron_graph* g)
     const int32_t D = std::max(g->max_outdeg, 2);
     hipStream_t s = g->stream;
     int64_t* acct = &g->device_bytes;
-    if (!g->d_rows_off) {
-        if ((st = dalloc(&g->d_rows_off, (size_t)g->n + 1, acct, "row offsets")) ||
-            (st = dalloc(&g->d_arc_c, (size_t)g->m, acct, "arc sizes")) ||
-            (st = dalloc(&g->d_harcs, (size_t)g->m, acct, "heavy arcs")) ||
-            (st = dalloc(&g->d_hhist, (size_t)D + 1, acct, "arc histogram")) ||
-            (st = dalloc(&g->d_hscan, (size_t)D + 1, acct, "arc histogram")) ||
-            (st = dalloc(&g->d_hcur, (size_t)D + 1, acct, "arc histogram")))
-            return st;
-    }
+    if ((!g->d_rows_off && (st = dalloc(&g->d_rows_off, (size_t)g->n + 1, acct, "row offsets"))) ||
+        (!g->d_arc_c && (st = dalloc(&g->d_arc_c, (size_t)g->m, acct, "arc sizes"))) ||
+        (!g->d_harcs && (st = dalloc(&g->d_harcs, (size_t)g->m, acct, "heavy arcs"))) ||
+        (!g->d_hhist && (st = dalloc(&g->d_hhist, (size_t)D + 1, acct, "arc histogram"))) ||
+        (!g->d_hscan && (st = dalloc(&g->d_hscan, (size_t)D + 1, acct, "arc histogram"))) ||
+        (!g->d_hcur && (st = dalloc(&g->d_hcur, (size_t)D + 1, acct, "arc histogram"))))
+        return st;
     // row offsets: exclusive scan of d(u) * W(u) (outdeg buffer as scratch)
     e = launch_rows_len(g->n, g->d_dag_ptr, g->d_outdeg, s);
     if (e == hipSuccess) e = scan_exclusive(g->d_outdeg, g->d_rows_off, g->n, g->d_scan_ws, s);
@@ -276,7 +283,8 @@ citron_status ensure_buckets(citron_graph* g, int32_t k)
     const int32_t pct = g->tuning.split_pct;
     if (g->d_buckets[k] && g->bucket_split[k] == pct) return CITRON_OK;
     dfree(g->d_buckets[k]);
-    g->d_buckets[k] = nullptr;
+    g->device_bytes -= g->bucket_bytes[k];
+    g->bucket_bytes[k] = 0;
     const int32_t D = std::max(g->max_outdeg, 2);
     auto v_at_least = [&](int32_t x) -> int64_t {   // vertices with out-degree >= x
         if (x > D) return 0;
@@ -319,6 +327,7 @@ citron_status ensure_buckets(citron_graph* g, int32_t k)
     tab.push_back(0);
     citron_status st = dalloc(&g->d_buckets[k], tab.size(), &g->device_bytes, "item buckets");
     if (st) return st;
+    g->bucket_bytes[k] = (int64_t)(sizeof(int32_t) * tab.size());
     hipError_t e = hipMemcpy(g->d_buckets[k], tab.data(), sizeof(int32_t) * tab.size(), hipMemcpyHostToDevice);
     if (e != hipSuccess) return hip_fail(e, "item buckets");
     g->n_buckets[k] = nb;
@@ -613,11 +622,12 @@ citron_status citron_order(citron_graph* g)
     int64_t* acct = &g->device_bytes;
     citron_status st;
     g->scan_ws_ints = scan_workspace_ints((int64_t)g->n + 1) + 64;
-    if ((st = dalloc(&g->d_outdeg, (size_t)g->n + 1, acct, "outdeg")) ||
-        (st = dalloc(&g->d_dag_ptr, (size_t)g->n + 1, acct, "dag_ptr")) ||
-        (st = dalloc(&g->d_dag_col, (size_t)g->m, acct, "dag_col")) ||
-        (st = dalloc(&g->d_dag_src, (size_t)g->m, acct, "dag_src")) ||
-        (st = dalloc(&g->d_scan_ws, g->scan_ws_ints, acct, "scan workspace")))
+    // a call that failed part-way keeps what it allocated; a retry reuses it
+    if ((!g->d_outdeg && (st = dalloc(&g->d_outdeg, (size_t)g->n + 1, acct, "outdeg"))) ||
+        (!g->d_dag_ptr && (st = dalloc(&g->d_dag_ptr, (size_t)g->n + 1, acct, "dag_ptr"))) ||
+        (!g->d_dag_col && (st = dalloc(&g->d_dag_col, (size_t)g->m, acct, "dag_col"))) ||
+        (!g->d_dag_src && (st = dalloc(&g->d_dag_src, (size_t)g->m, acct, "dag_src"))) ||
+        (!g->d_scan_ws && (st = dalloc(&g->d_scan_ws, g->scan_ws_ints, acct, "scan workspace"))))
         return st;
     hipStream_t s = g->stream;
     int32_t* mx = &g->d_small->max_outdeg;

@@ -70,8 +70,6 @@ struct citron_graph {
     citron::PlanHeader plan = {};
     citron_tuning plan_tuning = {};
     bool plan_valid = false;
-    int32_t* d_unit_ctr = nullptr;
-    int32_t unit_ctr_cap = 0;
     citron::QueryDesc* d_query = nullptr;
     unsigned long long* d_scratch = nullptr;
     int64_t scratch_bytes = 0;
@@ -96,6 +94,7 @@ struct citron_graph {
     // per k: the merged bucket table of the count's work items
     int32_t* d_buckets[CITRON_KMAX + 1] = {};
     int32_t bucket_split[CITRON_KMAX + 1] = {};   // split_pct each table was built with
+    int64_t bucket_bytes[CITRON_KMAX + 1] = {};   // device bytes of each table
     int32_t n_buckets[CITRON_KMAX + 1] = {};
     int32_t n_work[CITRON_KMAX + 1] = {};
     uint64_t build_stats[citron::kNumStats] = {};

@@ -49,13 +49,14 @@ struct Req {
     int32_t n_items = 0;
     int32_t issued = 0;       // items handed to steps
     int32_t retired = 0;      // items of retired steps
+    bool failed = false;      // a step with its items failed: issue no more
     int64_t footprint = 0;
     QueryDesc q;
 };
 
 // Lanes: a request with at most kFastItems items goes whole into one fast
 // step (at most kFastStepItems items); larger ones are sliced into heavy
-// steps of at most kItemsPerStep items, kItemsPerReq per request.
+// steps of at most kHeavyStepItems items, each step one request's slice.
 constexpr int32_t kFastItems = 4096;
 constexpr int32_t kFastStepItems = 65536;
 constexpr int32_t kHeavyStepItems = 1 << 20;
@@ -137,19 +138,20 @@ void complete(citron_server* s, Req& r, uint64_t count, citron_status st)
 }
 
 // Launch one step of a lane.  Fast: every fast request not yet issued,
-// whole, up to kFastStepItems items.  Heavy: a slice of every heavy request
-// with items left.  Returns false when the lane has nothing to issue.
+// whole, up to kFastStepItems items.  Heavy: the next slice of the first
+// heavy request (admission order) with items left.  Returns false when the
+// lane has nothing to issue.
 bool issue_step(citron_server* s, Step& st, bool fast, int wg, int32_t blocks)
 {
     int32_t with_work = 0;
     for (const Req& r : s->active)
-        if (r.fast == fast && r.issued < r.n_items) ++with_work;
+        if (r.fast == fast && !r.failed && r.issued < r.n_items) ++with_work;
     if (with_work == 0) return false;
     const int32_t cap = fast ? kFastStepItems : kHeavyStepItems;
     int32_t total = 0, maxk = 4, nq = 0;
     st.parts.clear();
     for (Req& r : s->active) {   // admission order
-        if (r.fast != fast || r.issued >= r.n_items) continue;
+        if (r.fast != fast || r.failed || r.issued >= r.n_items) continue;
         if (total >= cap) break;
         int32_t take = r.n_items - r.issued;
         if (fast && total + take > cap && total > 0) break;
@@ -191,14 +193,19 @@ bool issue_step(citron_server* s, Step& st, bool fast, int wg, int32_t blocks)
     return true;
 }
 
-// Retire a step: credit its items to their requests.
+// Retire a step: credit its items to their requests.  A failed step marks
+// its requests failed; they finish once every step holding their items has
+// retired, so that no step still adds into a slot that is handed on.
 void retire_step(citron_server* s, Step& st)
 {
     hipError_t e = st.err;
     if (e == hipSuccess) e = hipEventSynchronize(st.done);
     for (const auto& pr : st.parts)
         for (Req& r : s->active)
-            if (r.id == pr.first) r.retired = (e == hipSuccess && r.retired >= 0) ? r.retired + pr.second : -1;
+            if (r.id == pr.first) {
+                r.retired += pr.second;
+                if (e != hipSuccess) r.failed = true;
+            }
     if (e != hipSuccess) s->worker_error = hipGetErrorString(e);
     st.parts.clear();
 }
@@ -323,12 +330,12 @@ void worker_main(citron_server* s)
         std::vector<Req> still;
         std::vector<Req> fin;
         for (Req& r : s->active) {
-            if (r.retired == r.n_items || r.retired < 0) fin.push_back(r);
+            if (r.retired == r.n_items || (r.failed && r.retired == r.issued)) fin.push_back(r);
             else still.push_back(r);
         }
         hipError_t e = hipSuccess;
         for (const Req& r : fin) {
-            if (r.retired < 0) continue;
+            if (r.failed) continue;
             if (e == hipSuccess)
                 e = hipMemcpyAsync(s->h_acc + r.slot, s->d_acc + r.slot, sizeof(unsigned long long),
                                    hipMemcpyDeviceToHost, s->ctl);
@@ -340,7 +347,7 @@ void worker_main(citron_server* s)
         if (e != hipSuccess) s->worker_error = hipGetErrorString(e);
         std::lock_guard<std::mutex> lock(s->mu);
         for (Req& r : fin) {
-            if (r.retired < 0 || e != hipSuccess) complete(s, r, 0, CITRON_EDEVICE);
+            if (r.failed || e != hipSuccess) complete(s, r, 0, CITRON_EDEVICE);
             else complete(s, r, s->h_acc[r.slot], s->h_ovf[r.slot] ? CITRON_EOVERFLOW : CITRON_OK);
             s->free_slots.push_back(r.slot);
             s->used -= r.footprint;
