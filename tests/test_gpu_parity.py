@@ -69,7 +69,8 @@ def _esym(parts, k):
 
 def test_closed_forms(citron_gpu):
     """Expected values are the closed forms themselves (complete graphs,
-    Turan graphs, bipartite graphs, wheels, disjoint cliques, empty)."""
+    Turan graphs, bipartite graphs, wheels, disjoint cliques, Kneser and
+    Paley graphs, empty)."""
     cases = [
         (gg.complete(30), lambda k: math.comb(30, k), 8),
         (gg.complete(64), lambda k: math.comb(64, k), 6),
@@ -82,6 +83,10 @@ def test_closed_forms(citron_gpu):
         (gg.wheel(50), lambda k: [0, 51, 100, 50][k] if k < 4 else 0, 8),
         (gg.disjoint_cliques([3, 10, 66, 129, 1]),
          lambda k: sum(math.comb(s, k) for s in [3, 10, 66, 129, 1]), 5),
+        # Kneser K(11,3): k pairwise disjoint 3-subsets of 11 elements
+        (gg.kneser(11, 3), lambda k: [1, 165, 4620, 15400][k] if k < 4 else 0, 7),
+        # Paley(101): strongly regular, q(q-1)/4 edges, q(q-1)(q-5)/48 triangles
+        (gg.paley(101), lambda k: [1, 101, 2525, 20200][k], 3),
         (gg.empty(5), lambda k: 5 if k == 1 else 0, 8),
         (gg.empty(0), lambda k: 0, 8),
     ]
