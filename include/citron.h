@@ -111,7 +111,11 @@ citron_status citron_order(citron_graph* g);
 /* Counting phase: number of k-cliques of the graph, 1 <= k <= CITRON_KMAX.
  * k = 1 gives n, k = 2 gives m.  Requires ORDERED (else CITRON_ESTATE).
  * Returns 0 on error; on CITRON_EOVERFLOW returns the count mod 2^64.
- * st may be NULL. */
+ * The first count with k >= 3 builds the graph's subgraph rows (kept for
+ * later counts): CITRON_EINVAL if a DAG out-degree exceeds 4096 or the rows,
+ * the sum over vertices of d(u) * ceil(d(u)/64) 64-bit words with d(u) the
+ * out-degree, reach 2^31 words; CITRON_ENOMEM if they do not fit in device
+ * memory.  st may be NULL. */
 uint64_t citron_count(citron_graph* g, int32_t k, citron_status* st);
 
 /* As citron_count, and also writes per_arc[e] = the number of k-cliques

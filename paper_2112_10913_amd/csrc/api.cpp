@@ -202,6 +202,22 @@ citron_status ensure_rows(citron_graph* g)
         (!g->d_hscan && (st = dalloc(&g->d_hscan, (size_t)D + 1, acct, "arc histogram"))) ||
         (!g->d_hcur && (st = dalloc(&g->d_hcur, (size_t)D + 1, acct, "arc histogram"))))
         return st;
+    // Row offsets are int32, so the rows of all vertices, sum over u of
+    // d(u) * ceil(d(u)/64) words, must stay below 2^31.  That sum is at most
+    // m * ceil(D/64); only when this bound does not settle it is the exact
+    // sum taken, on the host from the DAG offsets.
+    if ((int64_t)g->m * ((g->max_outdeg + 63) / 64) >= (1LL << 31)) {
+        std::vector<int32_t> ptr((size_t)g->n + 1);
+        e = hipMemcpyAsync(ptr.data(), g->d_dag_ptr, sizeof(int32_t) * ptr.size(), hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        if (e != hipSuccess) return hip_fail(e, "row sizes");
+        int64_t total = 0;
+        for (int32_t u = 0; u < g->n; ++u) {
+            const int64_t d = ptr[(size_t)u + 1] - ptr[(size_t)u];
+            total += d * ((d + 63) / 64);
+        }
+        if (total >= (1LL << 31)) return fail(CITRON_EINVAL, "subgraph rows exceed 2^31 words");
+    }
     // row offsets: exclusive scan of d(u) * W(u) (outdeg buffer as scratch)
     e = launch_rows_len(g->n, g->d_dag_ptr, g->d_outdeg, s);
     if (e == hipSuccess) e = scan_exclusive(g->d_outdeg, g->d_rows_off, g->n, g->d_scan_ws, s);
