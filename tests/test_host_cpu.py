@@ -86,3 +86,16 @@ def test_traffic_summary_bookkeeping():
         pytest.skip("the HBM counter summary was taken on other kernel code: traffic is reported as null")
     v = b.traffic_per_launch([5, 6, 7])
     assert v is not None and v > 0
+
+
+def test_bench_refuses_more_than_one_gpu():
+    # one GPU only: the refusal comes before anything touches a device
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    for argv, env in ((["--gpus", "2"], {}), ([], {"WORLD_SIZE": "2"})):
+        r = subprocess.run([sys.executable, os.path.join(root, "bench.py"), *argv], capture_output=True,
+                           text=True, timeout=120, env={**os.environ, **env})
+        assert r.returncode == 2, r.stderr
+        assert "one GPU only" in r.stderr
+        assert r.stdout == ""
