@@ -161,6 +161,18 @@ def run_batch(args, citron, gg, torch, graphs):
     print(json.dumps(line), flush=True)
 
 
+def latency_breakdown(req, results, classes):
+    """Arrival-to-completion latency per (graph class, k): request i of
+    ``req`` is (graph index, k), results carry its index as their tag, and
+    classes[graph index] names the graph's class (e.g. its R-MAT scale)."""
+    groups = {}
+    for r in results:
+        gi, k = req[r["tag"]]
+        groups.setdefault((classes[gi], k), []).append((r["t_done_ns"] - r["t_submit_ns"]) / 1e6)
+    return [{"graph": c, "k": k, "n": len(v), "p50_ms": float(np.percentile(v, 50)),
+             "p99_ms": float(np.percentile(v, 99))} for (c, k), v in sorted(groups.items())]
+
+
 def run_serve(args, citron, gg, torch):
     """Served form: resident graphs, Poisson arrivals of (graph, k) requests,
     continuous batching; latency percentiles and counts/s, against the same
@@ -170,6 +182,7 @@ def run_serve(args, citron, gg, torch):
     graphs = gg.serve_suite(count=args.serve_graphs, seed0=5000, scale_min=12,
                             scale_max=args.serve_scale_max, big=big)
     log(f"generated {len(graphs)} graphs in {time.perf_counter() - t:.1f} s")
+    classes = [x.name.split("_")[0] for x in graphs[:-1]] + ["chunglu22" if args.serve_big else "rmat17"]
     hs = []
     for x in graphs:
         h = citron.Graph.from_csr(x.row_ptr, x.col).order()
@@ -237,7 +250,8 @@ def run_serve(args, citron, gg, torch):
              "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
              "fifo_plain_p50_ms": float(np.percentile(fifo, 50)),
              "fifo_plain_p99_ms": float(np.percentile(fifo, 99)),
-             "fifo_plain_rps": nreq / clock}
+             "fifo_plain_rps": nreq / clock,
+             "by_graph_k": latency_breakdown(req, res, classes)}
         log(f"  load {frac}: {p}")
         points.append(p)
     srv.close()

@@ -92,10 +92,21 @@ def test_bench_refuses_more_than_one_gpu():
     # one GPU only: the refusal comes before anything touches a device
     import subprocess
     import sys
-    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    root = ROOT
     for argv, env in ((["--gpus", "2"], {}), ([], {"WORLD_SIZE": "2"})):
         r = subprocess.run([sys.executable, os.path.join(root, "bench.py"), *argv], capture_output=True,
                            text=True, timeout=120, env={**os.environ, **env})
         assert r.returncode == 2, r.stderr
         assert "one GPU only" in r.stderr
         assert r.stdout == ""
+
+
+def test_served_latency_breakdown():
+    b = _bench()
+    req = [(0, 3), (1, 5), (0, 3), (1, 5), (0, 4)]
+    ms = [1.0, 10.0, 3.0, 30.0, 7.0]
+    res = [{"tag": i, "t_submit_ns": 1000, "t_done_ns": 1000 + int(x * 1e6)} for i, x in enumerate(ms)]
+    out = b.latency_breakdown(req, res[::-1], ["rmat12", "rmat16"])
+    assert [(e["graph"], e["k"], e["n"]) for e in out] == [("rmat12", 3, 2), ("rmat12", 4, 1), ("rmat16", 5, 2)]
+    assert out[0]["p50_ms"] == 2.0 and out[1]["p99_ms"] == 7.0
+    assert abs(out[2]["p99_ms"] - (10.0 + 0.99 * 20.0)) < 1e-9
