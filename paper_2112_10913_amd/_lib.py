@@ -269,7 +269,10 @@ class Graph:
         torch = _torch()
         a = torch.as_tensor(np.ascontiguousarray(arcs, dtype=np.int32)).cuda()
         n = int(a.numel())
-        out = torch.zeros(max(n, 1), dtype=torch.int64, device="cuda")
+        out = torch.empty(max(n, 1), dtype=torch.int64, device="cuda")   # every entry is written
+        # the arc list is copied on torch's current stream; the library works
+        # on the graph's stream, which need not be the same one
+        torch.cuda.current_stream().synchronize()
         st = ctypes.c_int32(0)
         load_library().citron_count_arcs(self._handle(), int(k), a.data_ptr(), n, out.data_ptr(),
                                          ctypes.byref(st))
