@@ -23,8 +23,9 @@
  *     returned modulo 2^64 with status CITRON_EOVERFLOW.  The flag does not
  *     depend on the order of additions: with non-negative addends some
  *     addition carries iff the exact total is >= 2^64.
- *   - Vertex ids and CSR offsets are int32_t; the undirected CSR may hold at
- *     most 2^31 - 1 entries (that is, fewer than 2^30 undirected edges).
+ *   - Vertex ids and CSR offsets are int32_t; a graph has fewer than 2^26
+ *     vertices and its undirected CSR at most 2^31 - 1 entries (that is,
+ *     fewer than 2^30 undirected edges).
  *   - All device work runs on the stream the graph was loaded with.  Calls
  *     that return results to the host synchronise that stream.
  *   - Different graphs may be used from different host threads at once.  A
@@ -87,7 +88,8 @@ typedef struct {
 /* ------------------------------------------------------------- graphs */
 
 /* Load a simple undirected graph given as CSR and copy it to the device.
- *   n        number of vertices, 0 <= n < 2^31
+ *   n        number of vertices, 0 <= n < 2^26 (the ordering kernels run
+ *            one 64-wide wave per vertex in a single dispatch)
  *   nnz      number of CSR entries = 2m (each undirected edge twice)
  *   row_ptr  int32[n+1], row_ptr[0] = 0, non-decreasing, row_ptr[n] = nnz
  *   col_idx  int32[nnz]; row u lists the neighbours of u strictly

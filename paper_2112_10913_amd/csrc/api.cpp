@@ -557,7 +557,9 @@ citron_status citron_load_csr(int32_t n, int64_t nnz, const int32_t* row_ptr, co
 {
     if (!out) return fail(CITRON_EINVAL, "out is NULL");
     *out = nullptr;
-    if (n < 0) return fail(CITRON_EINVAL, "n must be >= 0");
+    // the ordering and validation kernels give each vertex one wave: n * 64
+    // work-items must fit a dispatch's 32-bit grid size
+    if (n < 0 || n >= (1 << 26)) return fail(CITRON_EINVAL, "n must be in 0..2^26-1");
     if (nnz < 0 || nnz > 0x7fffffffLL) return fail(CITRON_EINVAL, "nnz must be in 0..2^31-1");
     if (nnz % 2) return fail(CITRON_EINVAL, "nnz must be even for a symmetric graph");
     if (!row_ptr) return fail(CITRON_EINVAL, "row_ptr is NULL");

@@ -62,3 +62,16 @@ def test_null_arguments_are_rejected_without_a_gpu(lib):
     lib.citron_free(None)
     lib.citron_last_error.restype = ctypes.c_char_p
     assert b"NULL" in lib.citron_last_error()
+
+
+def test_vertex_count_limit_is_checked_before_any_device_call(lib):
+    import numpy as np
+    rp = np.zeros(2, np.int32)
+    out = ctypes.c_void_p()
+    lib.citron_load_csr.argtypes = [ctypes.c_int32, ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p,
+                                    ctypes.c_uint32, ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p)]
+    lib.citron_last_error.restype = ctypes.c_char_p
+    for n in (1 << 26, -1):
+        assert lib.citron_load_csr(n, 0, rp.ctypes.data, None, 0, None, ctypes.byref(out)) == 1
+        assert out.value is None
+        assert b"2^26" in lib.citron_last_error()
