@@ -26,8 +26,14 @@
  *   - Vertex ids and CSR offsets are int32_t; a graph has fewer than 2^26
  *     vertices and its undirected CSR at most 2^31 - 1 entries (that is,
  *     fewer than 2^30 undirected edges).
- *   - All device work runs on the stream the graph was loaded with.  Calls
- *     that return results to the host synchronise that stream.
+ *   - The calls on one graph run their device work on the stream the graph
+ *     was loaded with, and those that return results to the host
+ *     synchronise it.  citron_count_batch runs on a non-blocking stream the
+ *     library keeps per device, the server on non-blocking streams of its
+ *     own; both return results only after their work has completed.  Work
+ *     the caller queued on a graph's stream is not waited for by these two:
+ *     finish it (for a device-pointer load, the producer of the CSR) before
+ *     calling them.
  *   - Different graphs may be used from different host threads at once.  A
  *     graph must not be freed while another thread uses it.  Count calls on
  *     one graph from several threads are serialised by the library.
