@@ -32,8 +32,7 @@
  *     library keeps per device, the server on non-blocking streams of its
  *     own; both return results only after their work has completed.  Work
  *     the caller queued on a graph's stream is not waited for by these two:
- *     finish it (for a device-pointer load, the producer of the CSR) before
- *     calling them.
+ *     finish it before calling them.
  *   - Different graphs may be used from different host threads at once.  A
  *     graph must not be freed while another thread uses it.  Count calls on
  *     one graph from several threads are serialised by the library.
