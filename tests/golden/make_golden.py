@@ -7,6 +7,7 @@ the parts is the count because the recursion is a sum over root vertices.
 Per-arc values are the edge-rooted counts of a seeded sample of arcs.
 
     python tests/golden/make_golden.py rmat14          # counts k = 3..6
+    python tests/golden/make_golden.py rmat14 --ks 7 8 # ~3 min on 8 processes
     python tests/golden/make_golden.py rmat20 --ks 3 4 --arcs 5 6 7 8
     python tests/golden/make_golden.py rmat20 --ks 5       # whole count, ~18 min on 8 processes
     python tests/golden/make_golden.py chunglu22 --ks 3 4 --arcs 5 6 7
