@@ -8,6 +8,8 @@ and by mathematics, never against the oracle itself:
 * triangles = trace(A^3)/6 computed by scipy sparse matrix products;
 * invariance of every count under vertex relabelling;
 * per-size visit counts equal to the counts at smaller k;
+* counts rooted at vertex classes and ranges adding up to the brute-force
+  count (how the stored whole counts of the large graphs were split);
 * DAG invariants of the degree ordering (Section IV).
 """
 import json
@@ -118,6 +120,22 @@ def test_brute_force_unpruned_and_rooted():
             got, _ = oracle.count_arcs(g.n, dptr, dcol, k, src, dcol)
             for u, v, c in zip(src, dcol, got):
                 assert int(c) == brute_rooted(g, k, int(u), int(v), less)
+
+
+def test_root_classes_and_ranges_add_up():
+    # the stored whole counts of the large graphs are sums of the counts
+    # rooted at vertex residue classes (one worker process per class); a
+    # clique is rooted at its lowest vertex, so the classes partition them
+    for g in _random_graphs(4, 9, 14, 21):
+        dptr, dcol = oracle.orient(g.n, g.row_ptr, g.col)
+        for k in range(3, 7):
+            want = brute_count(g, k)
+            for P in (1, 2, 3, 5):
+                parts = [oracle.count_dag(g.n, dptr, dcol, k, r, g.n, P)[0] for r in range(P)]
+                assert sum(parts) == want, (k, P)
+            h = g.n // 3
+            ranges = [oracle.count_dag(g.n, dptr, dcol, k, a, b)[0] for a, b in ((0, h), (h, g.n))]
+            assert sum(ranges) == want, k
 
 
 # ------------------------------------------------------------- closed forms
