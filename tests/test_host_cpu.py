@@ -110,3 +110,15 @@ def test_served_latency_breakdown():
     assert [(e["graph"], e["k"], e["n"]) for e in out] == [("rmat12", 3, 2), ("rmat12", 4, 1), ("rmat16", 5, 2)]
     assert out[0]["p50_ms"] == 2.0 and out[1]["p99_ms"] == 7.0
     assert abs(out[2]["p99_ms"] - (10.0 + 0.99 * 20.0)) < 1e-9
+
+
+@pytest.mark.parametrize("name", ["rmat14", "rmat20", "chunglu22"])
+def test_config_graphs_match_their_golden_files(name):
+    # the stored oracle values hold for exactly the graph the generator
+    # gives today (numpy PCG64 streams and the cleaning steps)
+    import json
+    with open(os.path.join(ROOT, "tests", "golden", f"{name}.json")) as f:
+        gold = json.load(f)
+    g = gg.config_graph(name)
+    assert (g.n, g.m) == (gold["n"], gold["m"])
+    assert g.sha256() == gold["sha256"]
