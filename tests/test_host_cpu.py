@@ -122,3 +122,55 @@ def test_config_graphs_match_their_golden_files(name):
     g = gg.config_graph(name)
     assert (g.n, g.m) == (gold["n"], gold["m"])
     assert g.sha256() == gold["sha256"]
+
+
+class _StubGraph:
+    """Stands in for a device graph: only the tuning the autotuner sets."""
+
+    def __init__(self, n, m):
+        from paper_2112_10913_amd import Tuning
+        self.n, self.m = n, m
+        self.t = Tuning(split_pct=100)
+
+    def get_tuning(self):
+        from dataclasses import replace
+        return replace(self.t)
+
+    def set_tuning(self, t):
+        self.t = t
+
+
+def test_autotune_picks_the_fastest_caches_it_and_rejects_changed_counts(tmp_path, monkeypatch):
+    import paper_2112_10913_amd.autotune as at
+    from paper_2112_10913_amd import CitronError, Tuning
+    calls = []
+
+    def fake_batch(graphs, ks, tuning=None):
+        calls.append(tuning)
+        if tuning.wg_waves == 8:
+            raise CitronError(1, "refused")
+        if tuning.wg_waves == 1 and tuning.blocks_per_cu == 2:
+            at.time.sleep(0)                                 # the fast one
+        else:
+            at.time.sleep(0.01 * tuning.wg_waves)
+        return [7] * len(ks)
+
+    monkeypatch.setattr(at, "count_batch", fake_batch)
+    monkeypatch.setattr(at, "device_info", lambda: {"arch": "gfx950", "cus": 256, "lds_bytes": 163840})
+    gs = [_StubGraph(10, 20), _StubGraph(30, 40)]
+    trials = [Tuning(wg_waves=w, blocks_per_cu=b, split_pct=s)
+              for w, b, s in ((4, 2, 100), (1, 2, 50), (8, 1, 100), (2, 2, 200))]
+    cache = str(tmp_path / "tune.json")
+    best, rep = at.autotune(gs, [5, 6], reps=3, cache_path=cache, tunings=trials)
+    assert (best.wg_waves, best.blocks_per_cu, best.split_pct) == (1, 2, 50)
+    assert all(g.t.split_pct == 50 for g in gs)               # the schedule is set on the graphs
+    assert [t["seconds"] is None for t in rep["trials"]] == [False, False, True, False]
+    n_calls = len(calls)
+    again, rep2 = at.autotune(gs, [5, 6], cache_path=cache, tunings=trials)
+    assert rep2["cached"] and again == best and len(calls) == n_calls
+
+    def changing(graphs, ks, tuning=None):
+        return [tuning.wg_waves] * len(ks)
+    monkeypatch.setattr(at, "count_batch", changing)
+    with pytest.raises(RuntimeError, match="changed a count"):
+        at.autotune(gs, [5, 6], reps=1, use_cache=False, tunings=trials[:2])
