@@ -174,3 +174,13 @@ def test_autotune_picks_the_fastest_caches_it_and_rejects_changed_counts(tmp_pat
     monkeypatch.setattr(at, "count_batch", changing)
     with pytest.raises(RuntimeError, match="changed a count"):
         at.autotune(gs, [5, 6], reps=1, use_cache=False, tunings=trials[:2])
+
+
+def test_cpu_baseline_line():
+    b = _bench()
+    g = gg.rmat(12, 16, seed=5)
+    cb = b.cpu_baseline(g, 4, budget_s=0.4)
+    assert set(cb) >= {"value", "unit", "cores", "kind", "sample"}
+    assert cb["kind"] == "oracle" and cb["cores"] == 1 and cb["unit"] == "edges/s"
+    assert cb["value"] > 0 and "mod" in cb["sample"]
+    assert abs(cb["value"] * cb["est_full_graph_s"] - g.m) < 1e-6 * g.m
