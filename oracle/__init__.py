@@ -50,6 +50,9 @@ def _load():
                                           _i32p, _i32p, ctypes.c_int64, _u64p, _i32p]
         lib.oracle_arc_stats.argtypes = [ctypes.c_int32, _i32p, _i32p, ctypes.c_int32,
                                          _u64p, _u64p]
+        lib.oracle_list_dag.argtypes = [ctypes.c_int32, _i32p, _i32p, ctypes.c_int32,
+                                        ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                                        _i32p, ctypes.c_uint64, _u64p]
         _lib = lib
     return _lib
 
@@ -140,3 +143,29 @@ def arc_stats(n, dptr, dcol, k):
     _check(_load().oracle_arc_stats(n, pa, pb, k, st.ctypes.data_as(_u64p),
                                     hist.ctypes.data_as(_u64p)))
     return {name: int(v) for name, v in zip(STAT_NAMES, st)}, [int(x) for x in hist]
+
+
+def list_dag(n, dptr, dcol, k, first=0, last=None, step=1, cap=None):
+    """k-cliques rooted at vertices first, first+step, ... < last, as an
+    int32 array of shape (found, k), each row in increasing degree order;
+    returns (array, total).  At most ``cap`` rows are kept (default: all,
+    sized by a first pass that only counts them)."""
+    last = n if last is None else last
+    lib = _load()
+    a, pa = _i32(dptr)
+    b, pb = _i32(dcol if len(dcol) else np.zeros(1, np.int32))
+    total = ctypes.c_uint64(0)
+    if cap is None:
+        _check(lib.oracle_list_dag(n, pa, pb, k, first, last, step, None, 0, ctypes.byref(total)))
+        cap = int(total.value)
+    out = np.zeros((max(cap, 1), k), np.int32)
+    _check(lib.oracle_list_dag(n, pa, pb, k, first, last, step, out.ctypes.data_as(_i32p), cap,
+                               ctypes.byref(total)))
+    got = min(cap, int(total.value))
+    return out[:got], int(total.value)
+
+
+def list_cliques(g, k):
+    """All k-cliques of graph g (rows in increasing degree order)."""
+    dptr, dcol = orient(g.n, g.row_ptr, g.col)
+    return list_dag(g.n, dptr, dcol, k)[0]

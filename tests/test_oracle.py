@@ -373,3 +373,46 @@ def test_arc_stats_match_definitions(seed):
     a = sp.csr_matrix((np.ones(g.nnz), g.col, g.row_ptr), shape=(g.n, g.n))
     assert st["sum_s"] == round((a @ a @ a).diagonal().sum() / 6)
     assert st["arcs"] == g.m
+
+
+# ------------------------------------------------------------- listing
+
+def _brute_cliques(g, k):
+    from tests._brute import adjacency
+    a = adjacency(g)
+    return {sub for sub in combinations(range(g.n), k) if all(a[x, y] for x, y in combinations(sub, 2))}
+
+
+def _as_sets(rows):
+    return [tuple(sorted(int(x) for x in r)) for r in rows]
+
+
+@pytest.mark.parametrize("seed", [4, 5])
+def test_listing_is_the_set_of_cliques(seed):
+    for g in _random_graphs(6, 3, 13, seed):
+        deg = g.degrees()
+        for k in range(1, 8):
+            rows = oracle.list_cliques(g, k)
+            got = _as_sets(rows)
+            assert len(got) == len(set(got)), "a clique listed twice"
+            assert set(got) == _brute_cliques(g, k), (g.n, k)
+            for r in rows:      # each in increasing degree order (ties by id)
+                assert all((deg[x], x) < (deg[y], y) for x, y in zip(r[:-1], r[1:]))
+
+
+def test_listing_fig1_and_complete():
+    g = gg.fig1_example()
+    assert _as_sets(oracle.list_cliques(g, 4)) == [(0, 1, 3, 4)]
+    assert oracle.list_cliques(g, 5).shape == (0, 5)
+    assert sorted(_as_sets(oracle.list_cliques(gg.complete(9), 4))) == list(combinations(range(9), 4))
+
+
+def test_listing_roots_and_cap():
+    g = gg.rmat(8, 16, seed=7)
+    dptr, dcol = oracle.orient(g.n, g.row_ptr, g.col)
+    whole, total = oracle.list_dag(g.n, dptr, dcol, 4)
+    assert total == len(whole) == ocount(g, 4)
+    parts = [oracle.list_dag(g.n, dptr, dcol, 4, r, g.n, 3)[0] for r in range(3)]
+    assert sorted(_as_sets(np.concatenate(parts))) == sorted(_as_sets(whole))
+    head, t2 = oracle.list_dag(g.n, dptr, dcol, 4, cap=10)
+    assert t2 == total and np.array_equal(head, whole[:10])
