@@ -50,6 +50,8 @@ def _load():
                                           _i32p, _i32p, ctypes.c_int64, _u64p, _i32p]
         lib.oracle_arc_stats.argtypes = [ctypes.c_int32, _i32p, _i32p, ctypes.c_int32,
                                          _u64p, _u64p]
+        lib.oracle_core_rank.argtypes = [ctypes.c_int32, _i32p, _i32p, _i32p]
+        lib.oracle_orient_rank.argtypes = [ctypes.c_int32, _i32p, _i32p, _i32p, _i32p, _i32p]
         lib.oracle_list_dag.argtypes = [ctypes.c_int32, _i32p, _i32p, ctypes.c_int32,
                                         ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
                                         _i32p, ctypes.c_uint64, _u64p]
@@ -169,3 +171,29 @@ def list_cliques(g, k):
     """All k-cliques of graph g (rows in increasing degree order)."""
     dptr, dcol = orient(g.n, g.row_ptr, g.col)
     return list_dag(g.n, dptr, dcol, k)[0]
+
+
+def core_rank(n, row_ptr, col):
+    """Removal position of each vertex in the core ordering (Algorithm 1)."""
+    a, pa = _i32(row_ptr)
+    b, pb = _i32(col if len(col) else np.zeros(1, np.int32))
+    rank = np.zeros(max(n, 1), np.int32)
+    _check(_load().oracle_core_rank(n, pa, pb, rank.ctypes.data_as(_i32p)))
+    return rank[:n]
+
+
+def orient_rank(n, row_ptr, col, rank):
+    """(dag_ptr, dag_col) with u -> v iff rank[u] < rank[v]."""
+    a, pa = _i32(row_ptr)
+    b, pb = _i32(col if len(col) else np.zeros(1, np.int32))
+    r, pr = _i32(rank if len(rank) else np.zeros(1, np.int32))
+    m = int(a[n]) // 2
+    dptr = np.zeros(n + 1, np.int32)
+    dcol = np.zeros(max(m, 1), np.int32)
+    _check(_load().oracle_orient_rank(n, pa, pb, pr, dptr.ctypes.data_as(_i32p), dcol.ctypes.data_as(_i32p)))
+    return dptr, dcol[:m]
+
+
+def orient_core(g):
+    """The core-ordered DAG of graph g."""
+    return orient_rank(g.n, g.row_ptr, g.col, core_rank(g.n, g.row_ptr, g.col))

@@ -422,3 +422,98 @@ int oracle_list_dag(int32_t n, const int32_t* dptr, const int32_t* dcol, int32_t
     free(c.clique);
     return st;
 }
+
+/* ----------------------------------- core ordering (Section III, Alg. 1) */
+
+/* Core (degeneracy) ordering of Algorithm 1: repeatedly remove a vertex of
+ * smallest current degree (ties: smallest id) and lower its neighbours'
+ * degrees.  Reading of the algorithm's rank formula, which is garbled: the
+ * vertex removed first gets the lowest rank (rank = removal position), and
+ * arcs go from lower to higher rank, so each vertex points to the
+ * neighbours still present when it is removed; the maximum out-degree is
+ * then the degeneracy, the property the paper gives the ordering.  A binary
+ * heap of (degree, id) entries with stale entries skipped on pop. */
+typedef struct { int32_t deg, id; } heap_item;
+
+static int item_less(heap_item a, heap_item b)
+{
+    return a.deg < b.deg || (a.deg == b.deg && a.id < b.id);
+}
+
+static void heap_push(heap_item* h, int64_t* size, heap_item x)
+{
+    int64_t i = (*size)++;
+    h[i] = x;
+    while (i > 0) {
+        int64_t p = (i - 1) / 2;
+        if (!item_less(h[i], h[p])) break;
+        heap_item t = h[i]; h[i] = h[p]; h[p] = t;
+        i = p;
+    }
+}
+
+static heap_item heap_pop(heap_item* h, int64_t* size)
+{
+    heap_item top = h[0];
+    h[0] = h[--(*size)];
+    int64_t i = 0;
+    for (;;) {
+        int64_t l = 2 * i + 1, r = l + 1, s = i;
+        if (l < *size && item_less(h[l], h[s])) s = l;
+        if (r < *size && item_less(h[r], h[s])) s = r;
+        if (s == i) break;
+        heap_item t = h[i]; h[i] = h[s]; h[s] = t;
+        i = s;
+    }
+    return top;
+}
+
+/* rank[v] = position of v in the removal order (0 = removed first). */
+int oracle_core_rank(int32_t n, const int32_t* row_ptr, const int32_t* col, int32_t* rank)
+{
+    if (n < 0) return ORACLE_EINVAL;
+    int64_t nnz = row_ptr[n];
+    int32_t* deg = (int32_t*)malloc(sizeof(int32_t) * ((size_t)n + 1));
+    heap_item* h = (heap_item*)malloc(sizeof(heap_item) * ((size_t)(n + nnz) + 1));
+    if (!deg || !h) { free(deg); free(h); return ORACLE_ENOMEM; }
+    int64_t size = 0;
+    for (int32_t v = 0; v < n; ++v) {
+        deg[v] = (int32_t)(row_ptr[v + 1] - row_ptr[v]);
+        rank[v] = -1;
+        heap_item x = {deg[v], v};
+        heap_push(h, &size, x);
+    }
+    int32_t r = 0;
+    while (size > 0) {
+        heap_item x = heap_pop(h, &size);
+        if (rank[x.id] >= 0 || x.deg != deg[x.id]) continue;   /* stale */
+        rank[x.id] = r++;
+        for (int64_t e = row_ptr[x.id]; e < row_ptr[x.id + 1]; ++e) {
+            int32_t w = col[e];
+            if (rank[w] >= 0) continue;
+            deg[w] -= 1;
+            heap_item y = {deg[w], w};
+            heap_push(h, &size, y);
+        }
+    }
+    free(deg);
+    free(h);
+    return ORACLE_OK;
+}
+
+/* The DAG of a rank: u -> v iff rank[u] < rank[v]; out-lists keep the
+ * ascending id order of the input rows.  dag_ptr int32[n+1], dag_col
+ * int32[m]. */
+int oracle_orient_rank(int32_t n, const int32_t* row_ptr, const int32_t* col, const int32_t* rank,
+                       int32_t* dag_ptr, int32_t* dag_col)
+{
+    if (n < 0) return ORACLE_EINVAL;
+    dag_ptr[0] = 0;
+    for (int32_t u = 0; u < n; ++u) {
+        int32_t c = 0;
+        for (int64_t e = row_ptr[u]; e < row_ptr[u + 1]; ++e)
+            if (rank[u] < rank[col[e]]) dag_col[dag_ptr[u] + c++] = col[e];
+        dag_ptr[u + 1] = dag_ptr[u] + c;
+    }
+    return ORACLE_OK;
+}

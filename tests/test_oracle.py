@@ -10,7 +10,10 @@ and by mathematics, never against the oracle itself:
 * per-size visit counts equal to the counts at smaller k;
 * counts rooted at vertex classes and ranges adding up to the brute-force
   count (how the stored whole counts of the large graphs were split);
-* DAG invariants of the degree ordering (Section IV).
+* DAG invariants of the degree ordering (Section IV);
+* listing: the listed cliques equal brute-force enumeration as a set;
+* core ordering (Algorithm 1): maximum out-degree equals the brute-force
+  degeneracy and closed forms; counts on its DAG equal brute force.
 """
 import json
 import math
@@ -416,3 +419,52 @@ def test_listing_roots_and_cap():
     assert sorted(_as_sets(np.concatenate(parts))) == sorted(_as_sets(whole))
     head, t2 = oracle.list_dag(g.n, dptr, dcol, 4, cap=10)
     assert t2 == total and np.array_equal(head, whole[:10])
+
+
+# ------------------------------------------------------- core ordering
+
+def _brute_degeneracy(g):
+    # the largest minimum degree over all induced subgraphs (definition)
+    from tests._brute import adjacency
+    a = adjacency(g)
+    best = 0
+    for mask in range(1, 1 << g.n):
+        vs = [v for v in range(g.n) if mask >> v & 1]
+        best = max(best, min(int(a[v, vs].sum()) for v in vs))
+    return best
+
+
+def _core_outdeg(g):
+    dptr, dcol = oracle.orient_core(g)
+    return int(np.diff(dptr).max(initial=0)), dptr, dcol
+
+
+@pytest.mark.parametrize("seed", [8, 9])
+def test_core_ordering_reaches_the_degeneracy(seed):
+    for g in _random_graphs(5, 2, 12, seed):
+        mx, dptr, dcol = _core_outdeg(g)
+        assert mx == _brute_degeneracy(g), g.n
+        assert int(dptr[-1]) == g.m
+        for k in range(1, 7):     # any acyclic orientation counts every clique once
+            assert oracle.count_dag(g.n, dptr, dcol, k)[0] == brute_count(g, k), k
+
+
+@pytest.mark.parametrize("g,degeneracy", [
+    (gg.complete(12), 11), (gg.complete_bipartite(4, 9), 4), (gg.grid(5, 7), 2),
+    (gg.hypercube(5), 5), (gg.wheel(9), 3), (gg.paley(29), 14), (gg.turan(12, 4), 9),
+    (gg.empty(6), 0)])
+def test_core_ordering_closed_forms(g, degeneracy):
+    # complete K_n: n-1; K_a,b: min(a,b); grids: 2; d-regular graphs: d;
+    # wheels: 3; Turan T(12,4) is 9-regular
+    mx, dptr, dcol = _core_outdeg(g)
+    assert mx == degeneracy
+    rank = oracle.core_rank(g.n, g.row_ptr, g.col)
+    assert sorted(rank.tolist()) == list(range(g.n))
+
+
+def test_core_ordering_never_exceeds_the_degree_ordering():
+    g = gg.rmat(12, 16, seed=5)
+    core_mx, dptr, dcol = _core_outdeg(g)
+    deg_mx = int(np.diff(oracle.orient(g.n, g.row_ptr, g.col)[0]).max())
+    assert core_mx <= deg_mx
+    assert oracle.count_dag(g.n, dptr, dcol, 5)[0] == ocount(g, 5)
