@@ -52,6 +52,9 @@ def _load():
                                          _u64p, _u64p]
         lib.oracle_core_rank.argtypes = [ctypes.c_int32, _i32p, _i32p, _i32p]
         lib.oracle_orient_rank.argtypes = [ctypes.c_int32, _i32p, _i32p, _i32p, _i32p, _i32p]
+        lib.oracle_list_arcs.argtypes = [ctypes.c_int32, _i32p, _i32p, ctypes.c_int32,
+                                         _i32p, _i32p, ctypes.c_int64, _u64p, _i32p,
+                                         ctypes.c_uint64, _u64p]
         lib.oracle_list_dag.argtypes = [ctypes.c_int32, _i32p, _i32p, ctypes.c_int32,
                                         ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
                                         _i32p, ctypes.c_uint64, _u64p]
@@ -197,3 +200,24 @@ def orient_rank(n, row_ptr, col, rank):
 def orient_core(g):
     """The core-ordered DAG of graph g."""
     return orient_rank(g.n, g.row_ptr, g.col, core_rank(g.n, g.row_ptr, g.col))
+
+
+def list_arcs(n, dptr, dcol, k, arc_u, arc_v):
+    """Edge-rooted listing: (cliques as an int32 array (total, k), per-arc
+    clique counts as uint64); the cliques of arc i come before those of arc
+    i+1, each starting with the arc's two vertices."""
+    lib = _load()
+    a, pa = _i32(dptr)
+    b, pb = _i32(dcol if len(dcol) else np.zeros(1, np.int32))
+    u, pu = _i32(arc_u if len(arc_u) else np.zeros(1, np.int32))
+    v, pv = _i32(arc_v if len(arc_v) else np.zeros(1, np.int32))
+    na = len(arc_u)
+    per_arc = np.zeros(max(na, 1), np.uint64)
+    total = ctypes.c_uint64(0)
+    _check(lib.oracle_list_arcs(n, pa, pb, k, pu, pv, na, per_arc.ctypes.data_as(_u64p), None, 0,
+                                ctypes.byref(total)))
+    cap = int(total.value)
+    out = np.zeros((max(cap, 1), k), np.int32)
+    _check(lib.oracle_list_arcs(n, pa, pb, k, pu, pv, na, per_arc.ctypes.data_as(_u64p),
+                                out.ctypes.data_as(_i32p), cap, ctypes.byref(total)))
+    return out[:cap], per_arc[:na]

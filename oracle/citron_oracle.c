@@ -385,6 +385,35 @@ static void list_in(list_ctx* c, const int32_t* cand, int64_t s, int r, int have
     }
 }
 
+static int list_init(list_ctx* c, int32_t n, const int32_t* dptr, const int32_t* dcol, int32_t k,
+                     int32_t* out, uint64_t cap)
+{
+    memset(c, 0, sizeof(*c));
+    c->dptr = dptr;
+    c->dcol = dcol;
+    c->k = k;
+    c->out = out;
+    c->cap = cap;
+    c->clique = (int32_t*)malloc(sizeof(int32_t) * (size_t)k);
+    /* one candidate buffer per level, plus one for an arc's C_uv */
+    c->level_buf = (int32_t**)calloc((size_t)k + 2, sizeof(int32_t*));
+    if (!c->clique || !c->level_buf) return ORACLE_ENOMEM;
+    int32_t mx = max_outdeg_of(n, dptr);
+    for (int r = 0; r <= k + 1; ++r) {
+        c->level_buf[r] = (int32_t*)malloc(sizeof(int32_t) * ((size_t)mx + 1));
+        if (!c->level_buf[r]) return ORACLE_ENOMEM;
+    }
+    return ORACLE_OK;
+}
+
+static void list_free(list_ctx* c)
+{
+    if (c->level_buf)
+        for (int r = 0; r <= c->k + 1; ++r) free(c->level_buf[r]);
+    free(c->level_buf);
+    free(c->clique);
+}
+
 /* Lists the k-cliques rooted at u = first, first+step, ... < last of the
  * oriented graph (dptr, dcol): out receives min(total, cap) cliques of k
  * int32 each, in the order found; *total the number of cliques.  k >= 1. */
@@ -394,20 +423,7 @@ int oracle_list_dag(int32_t n, const int32_t* dptr, const int32_t* dcol, int32_t
 {
     if (k < 1 || step < 1 || first < 0 || last > n || (cap > 0 && !out)) return ORACLE_EINVAL;
     list_ctx c;
-    memset(&c, 0, sizeof(c));
-    c.dptr = dptr;
-    c.dcol = dcol;
-    c.k = k;
-    c.out = out;
-    c.cap = cap;
-    c.clique = (int32_t*)malloc(sizeof(int32_t) * (size_t)k);
-    c.level_buf = (int32_t**)calloc((size_t)k + 1, sizeof(int32_t*));
-    int st = (c.clique && c.level_buf) ? ORACLE_OK : ORACLE_ENOMEM;
-    int32_t mx = max_outdeg_of(n, dptr);
-    for (int r = 0; st == ORACLE_OK && r <= k; ++r) {
-        c.level_buf[r] = (int32_t*)malloc(sizeof(int32_t) * ((size_t)mx + 1));
-        if (!c.level_buf[r]) st = ORACLE_ENOMEM;
-    }
+    int st = list_init(&c, n, dptr, dcol, k, out, cap);
     if (st == ORACLE_OK) {
         for (int32_t u = first; u < last; u += step) {
             c.clique[0] = u;
@@ -416,10 +432,41 @@ int oracle_list_dag(int32_t n, const int32_t* dptr, const int32_t* dcol, int32_t
         }
         *total = c.total;
     }
-    if (c.level_buf)
-        for (int r = 0; r <= k; ++r) free(c.level_buf[r]);
-    free(c.level_buf);
-    free(c.clique);
+    list_free(&c);
+    return st;
+}
+
+/* Edge-rooted listing: for each listed arc u -> v of the oriented graph, in
+ * the order given, the k-cliques whose two lowest vertices are u and v
+ * (u, v and a (k-2)-clique of the subgraph induced on N->(u) cap N->(v)).
+ * per_arc[i] receives the number of cliques of arc i; out and *total as in
+ * oracle_list_dag.  k >= 2. */
+int oracle_list_arcs(int32_t n, const int32_t* dptr, const int32_t* dcol, int32_t k,
+                     const int32_t* arc_u, const int32_t* arc_v, int64_t narcs,
+                     uint64_t* per_arc, int32_t* out, uint64_t cap, uint64_t* total)
+{
+    if (k < 2 || narcs < 0 || (cap > 0 && !out)) return ORACLE_EINVAL;
+    list_ctx c;
+    int st = list_init(&c, n, dptr, dcol, k, out, cap);
+    if (st == ORACLE_OK) {
+        int32_t* cand = c.level_buf[k + 1];
+        for (int64_t i = 0; i < narcs; ++i) {
+            int32_t u = arc_u[i], v = arc_v[i];
+            uint64_t before = c.total;
+            c.clique[0] = u;
+            c.clique[1] = v;
+            if (k == 2) {
+                emit(&c);
+            } else {
+                int64_t s = intersect(dcol + dptr[u], dptr[u + 1] - dptr[u],
+                                      dcol + dptr[v], dptr[v + 1] - dptr[v], cand);
+                list_in(&c, cand, s, k - 2, 2);
+            }
+            per_arc[i] = c.total - before;
+        }
+        *total = c.total;
+    }
+    list_free(&c);
     return st;
 }
 

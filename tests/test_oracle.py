@@ -468,3 +468,21 @@ def test_core_ordering_never_exceeds_the_degree_ordering():
     deg_mx = int(np.diff(oracle.orient(g.n, g.row_ptr, g.col)[0]).max())
     assert core_mx <= deg_mx
     assert oracle.count_dag(g.n, dptr, dcol, 5)[0] == ocount(g, 5)
+
+
+def test_edge_rooted_listing():
+    for g in _random_graphs(5, 4, 12, 31):
+        dptr, dcol = oracle.orient(g.n, g.row_ptr, g.col)
+        deg = g.degrees()
+        src = np.repeat(np.arange(g.n), np.diff(dptr)).astype(np.int32)
+        for k in range(2, 7):
+            rows, per_arc = oracle.list_arcs(g.n, dptr, dcol, k, src, dcol)
+            got = _as_sets(rows)
+            assert len(got) == len(set(got)) and set(got) == _brute_cliques(g, k), (g.n, k)
+            counts, _ = oracle.count_arcs(g.n, dptr, dcol, k, src, dcol)
+            assert per_arc.tolist() == [int(c) for c in counts]
+            starts = np.concatenate([[0], np.cumsum(per_arc.astype(np.int64))])
+            for i, (u, v) in enumerate(zip(src, dcol)):
+                for r in rows[starts[i]:starts[i + 1]]:
+                    assert (r[0], r[1]) == (u, v)
+                    assert all((deg[x], x) < (deg[y], y) for x, y in zip(r[:-1], r[1:]))
