@@ -10,6 +10,8 @@
 
 using namespace citron;
 
+static_assert(kNumStats == CITRON_NSTATS, "work statistics slots of the kernel and of the ABI");
+
 namespace citron {
 
 thread_local std::string g_last_error;
@@ -435,7 +437,7 @@ struct ListItems {
 // One query through the count kernel; synchronous on the graph's stream.
 static citron_status run_single(citron_graph* g, int32_t k, unsigned long long* per_arc, bool stats,
                                 uint64_t* out_count, const int32_t* arc_list = nullptr, int32_t n_list = 0,
-                                int32_t part = 0, int32_t nparts = 1)
+                                int32_t part = 0, int32_t nparts = 1, uint64_t* stats_out = nullptr)
 {
     std::lock_guard<std::mutex> lock(g->mu);
     hipError_t e = hipSetDevice(g->device);
@@ -542,6 +544,15 @@ static citron_status run_single(citron_graph* g, int32_t k, unsigned long long* 
     e = hipStreamSynchronize(s);
     if (e != hipSuccess) return hip_fail(e, "count kernel");
     *out_count = g->h_small->acc;
+    if (stats && stats_out) {
+        // copied while the graph is still locked: another call may reuse
+        // the pinned mirror as soon as the lock is released
+        memcpy(stats_out, g->h_small->stats, sizeof(uint64_t) * kNumStats);
+        stats_out[kStatVertices] = g->build_stats[kStatVertices];
+        stats_out[kStatRows] = g->build_stats[kStatRows];
+        stats_out[kStatEntries] = g->build_stats[kStatEntries];
+        stats_out[kStatBytes] = g->build_stats[kStatBytes];
+    }
     if (g->h_small->overflow) return fail(CITRON_EOVERFLOW, "count is >= 2^64; value is mod 2^64");
     return CITRON_OK;
 }
@@ -781,13 +792,8 @@ citron_status citron_work_stats(citron_graph* g, int32_t k, uint64_t* stats)
     if (st) return st;
     if (trivial) return CITRON_OK;
     uint64_t c = 0;
-    st = run_single(g, k, nullptr, true, &c);
+    st = run_single(g, k, nullptr, true, &c, nullptr, 0, 0, 1, stats);
     if (st && st != CITRON_EOVERFLOW) return st;
-    memcpy(stats, g->h_small->stats, sizeof(uint64_t) * CITRON_NSTATS);
-    stats[kStatVertices] = g->build_stats[kStatVertices];
-    stats[kStatRows] = g->build_stats[kStatRows];
-    stats[kStatEntries] = g->build_stats[kStatEntries];
-    stats[kStatBytes] = g->build_stats[kStatBytes];
     return CITRON_OK;
 }
 
