@@ -843,6 +843,7 @@ citron_status citron_set_tuning(citron_graph* g, const citron_tuning* t)
 citron_status citron_get_tuning(const citron_graph* g, citron_tuning* t)
 {
     if (!g || !t) return fail(CITRON_EINVAL, "NULL argument");
+    std::lock_guard<std::mutex> lock(const_cast<citron_graph*>(g)->mu);
     *t = g->tuning;
     return CITRON_OK;
 }
