@@ -44,6 +44,9 @@ def _load():
         lib.oracle_count_dag.argtypes = [ctypes.c_int32, _i32p, _i32p, ctypes.c_int32,
                                          ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
                                          ctypes.c_int32, _u64p, _i32p, _u64p]
+        lib.oracle_count_dag_from.argtypes = [ctypes.c_int32, _i32p, _i32p, ctypes.c_int32,
+                                              ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                                              ctypes.c_int32, ctypes.c_uint64, _u64p, _i32p, _u64p]
         lib.oracle_count.argtypes = [ctypes.c_int32, _i32p, _i32p, ctypes.c_int32,
                                      ctypes.c_int32, _u64p, _i32p, _u64p]
         lib.oracle_count_arcs.argtypes = [ctypes.c_int32, _i32p, _i32p, ctypes.c_int32,
@@ -91,17 +94,18 @@ def orient(n, row_ptr, col):
 
 
 def count_dag(n, dptr, dcol, k, first=0, last=None, step=1, prune=True,
-              visits=False):
-    """k-cliques rooted at vertices first, first+step, ... < last."""
+              visits=False, base=0):
+    """k-cliques rooted at vertices first, first+step, ... < last, added to
+    ``base`` (mod 2^64; the flag tells whether base + count >= 2^64)."""
     last = n if last is None else last
     a, pa = _i32(dptr)
     b, pb = _i32(dcol if len(dcol) else np.zeros(1, np.int32))
     cnt = ctypes.c_uint64(0)
     ovf = ctypes.c_int32(0)
     vis = np.zeros(k + 1, np.uint64) if visits else None
-    _check(_load().oracle_count_dag(n, pa, pb, k, first, last, step, int(prune),
-                                    ctypes.byref(cnt), ctypes.byref(ovf),
-                                    vis.ctypes.data_as(_u64p) if visits else None))
+    _check(_load().oracle_count_dag_from(n, pa, pb, k, first, last, step, int(prune), int(base),
+                                         ctypes.byref(cnt), ctypes.byref(ovf),
+                                         vis.ctypes.data_as(_u64p) if visits else None))
     if visits:
         return int(cnt.value), bool(ovf.value), [int(x) for x in vis]
     return int(cnt.value), bool(ovf.value)

@@ -217,11 +217,14 @@ static void ctx_free(count_ctx* c, int k)
 }
 
 /* Count k-cliques of the oriented graph (dptr, dcol) rooted at the vertices
- * u = first, first+step, ... < last (all of V for 0, 1, n).  k >= 1.
+ * u = first, first+step, ... < last (all of V for 0, 1, n), added to a
+ * starting value `base` (0 for a plain count; a base near 2^64 exercises the
+ * overflow flag: the flag is set iff base + the count is >= 2^64, the
+ * reading of the unstated counter width as uint64).  k >= 1.
  * visits: NULL or uint64[k+1]. */
-int oracle_count_dag(int32_t n, const int32_t* dptr, const int32_t* dcol, int32_t k,
-                     int32_t first, int32_t last, int32_t step, int32_t prune,
-                     uint64_t* count, int32_t* overflow, uint64_t* visits)
+int oracle_count_dag_from(int32_t n, const int32_t* dptr, const int32_t* dcol, int32_t k,
+                          int32_t first, int32_t last, int32_t step, int32_t prune,
+                          uint64_t base, uint64_t* count, int32_t* overflow, uint64_t* visits)
 {
     if (k < 1 || step < 1 || first < 0 || last > n) return ORACLE_EINVAL;
     count_ctx c;
@@ -229,6 +232,7 @@ int oracle_count_dag(int32_t n, const int32_t* dptr, const int32_t* dcol, int32_
         ctx_free(&c, k);
         return ORACLE_ENOMEM;
     }
+    c.count = base;
     for (int32_t u = first; u < last; u += step) {
         int64_t du = dptr[u + 1] - dptr[u];
         add_visits(&c, 1, 1);
@@ -239,6 +243,15 @@ int oracle_count_dag(int32_t n, const int32_t* dptr, const int32_t* dcol, int32_
     *overflow = c.overflow;
     ctx_free(&c, k);
     return ORACLE_OK;
+}
+
+/* The same, starting from 0. */
+int oracle_count_dag(int32_t n, const int32_t* dptr, const int32_t* dcol, int32_t k,
+                     int32_t first, int32_t last, int32_t step, int32_t prune,
+                     uint64_t* count, int32_t* overflow, uint64_t* visits)
+{
+    return oracle_count_dag_from(n, dptr, dcol, k, first, last, step, prune, 0, count, overflow,
+                                 visits);
 }
 
 /* Whole pipeline: orient, then count.  Visits as above. */

@@ -428,7 +428,10 @@ citron_status citron_server_add_graph(citron_server* s, citron_graph* g, int32_t
     if (g->device != s->device) return fail(CITRON_EINVAL, "graph and server live on different devices");
     {
         std::lock_guard<std::mutex> gl(g->mu);
-        if (g->max_outdeg >= 3) {   // rows are needed only when some k >= 4 can be nonzero
+        // the rows (and with them the triangle count that answers k = 3) are
+        // needed whenever some k >= 3 can be nonzero: a vertex with two
+        // out-neighbours roots a possible triangle
+        if (g->max_outdeg >= 2) {
             citron_status st = ensure_rows(g);
             if (st) return st;
         }

@@ -12,6 +12,13 @@ Per-arc values are the edge-rooted counts of a seeded sample of arcs.
     python tests/golden/make_golden.py rmat20 --ks 5       # whole count, ~18 min on 8 processes
     python tests/golden/make_golden.py chunglu22 --ks 3 4 --arcs 5 6 7
     python tests/golden/make_golden.py chunglu22 --ks 5    # whole count, ~13 min on 8 processes
+    python tests/golden/make_golden.py rmat20 --ks --work-model 5 6 7 8   # ~2 min
+
+The work model of a k (``--work-model``) is the oracle's per-arc statistics
+over the arcs that survive pruning (|C_uv| >= k - 2): the sums of
+d->(u) + d->(v), of |C_uv| and of the out-degrees of the candidates, from
+which the per-query algorithmic bytes of the merge-based construction are
+formed.
 """
 from __future__ import annotations
 
@@ -60,6 +67,12 @@ def _arc(args):
     return int(c[0]), bool(ovf), time.time() - t
 
 
+def _work_model(k):
+    g = _G["g"]
+    st, _ = oracle.arc_stats(g.n, _G["dptr"], _G["dcol"], k)
+    return st
+
+
 def sample_arcs(dptr, dcol, n_uniform, n_heavy, seed, heavy_outdeg=64):
     """Seeded uniform arcs plus arcs leaving vertices of out-degree > 64."""
     rng = np.random.default_rng(seed)
@@ -81,6 +94,7 @@ def main():
     ap.add_argument("--n-uniform", type=int, default=192)
     ap.add_argument("--n-heavy", type=int, default=64)
     ap.add_argument("--procs", type=int, default=os.cpu_count() or 1)
+    ap.add_argument("--work-model", type=int, nargs="*", default=[])
     args = ap.parse_args()
     out_path = os.path.join(os.path.dirname(os.path.abspath(__file__)), f"{args.name}.json")
     data = {}
@@ -97,6 +111,15 @@ def main():
                 max_outdeg=int(np.diff(_G["dptr"]).max(initial=0)),
                 generator="graphgen (numpy PCG64), numpy " + np.__version__)
     counts = data.setdefault("counts", {})
+    if args.work_model:
+        wm = data.setdefault("work_model", {})
+        with Pool(min(args.procs, len(args.work_model)), initializer=_init, initargs=(args.name, cache)) as pool:
+            res = pool.map(_work_model, args.work_model)
+        for k, st in zip(args.work_model, res):
+            wm[str(k)] = st
+            print(f"work model k={k}: {st}", flush=True)
+        with open(out_path, "w") as f:
+            json.dump(data, f, indent=1)
     P = args.procs
     with Pool(P, initializer=_init, initargs=(args.name, cache)) as pool:
         for k in args.ks:

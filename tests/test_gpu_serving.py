@@ -1,5 +1,5 @@
 """Served form: continuous batching over resident graphs.  Every result must
-equal the plain count exactly, whatever the mix it was served in."""
+equal the oracle's count exactly, whatever the mix it was served in."""
 import sys
 import time
 
@@ -22,37 +22,79 @@ def drain(srv, n, timeout=120.0):
     return out
 
 
+# k above which a graph's expected counts are not asked for (the oracle's
+# time on the CPU); requests draw k in 1..min(8, cap)
+KCAP = {2: 6}
+
+
 @pytest.fixture(scope="module")
 def graphs(citron_gpu):
-    gs = [gg.rmat(s, 16, seed=300 + s) for s in (10, 12, 13)] + [gg.erdos_renyi(4000, 30, seed=9),
-                                                                 gg.complete(40)]
+    """Resident graphs and their expected counts from the oracle (closed form
+    C(40, k) for the complete graph).  The handles are not counted before
+    they are served: the server must build what it needs itself."""
+    import math
+    import oracle
+    gs = [gg.rmat(10, 16, seed=310), gg.rmat(11, 16, seed=311), gg.rmat(13, 16, seed=313),
+          gg.erdos_renyi(4000, 30, seed=9), gg.complete(40)]
     hs = [citron_gpu.Graph.from_csr(g.row_ptr, g.col).order() for g in gs]
-    plain = {(i, k): h.count(k) for i, h in enumerate(hs) for k in range(1, 9)}
-    return hs, plain
+    want = {}
+    for i, g in enumerate(gs):
+        for k in range(1, KCAP.get(i, 8) + 1):
+            if i == 4:
+                want[(i, k)] = math.comb(40, k)
+            else:
+                c, ovf = oracle.count(g, k)
+                assert not ovf
+                want[(i, k)] = c
+    return hs, want
 
 
-def test_served_equals_plain_in_a_mix(citron_gpu, graphs):
-    hs, plain = graphs
+def test_served_equals_oracle_in_a_mix(citron_gpu, graphs):
+    hs, want = graphs
     srv = citron_gpu.Server(hbm_budget_bytes=1 << 30, max_slots=16)
     ids = [srv.add_graph(h) for h in hs]
     rng = np.random.default_rng(5)
-    reqs = [(int(rng.integers(len(ids))), int(rng.integers(1, 9))) for _ in range(200)]
+    reqs = []
+    for _ in range(200):
+        gi = int(rng.integers(len(ids)))
+        reqs.append((gi, int(rng.integers(1, KCAP.get(gi, 8) + 1))))
     for tag, (gi, k) in enumerate(reqs):
         srv.submit(ids[gi], k, tag)
         if tag % 17 == 0:
             time.sleep(0.002)          # arrivals while others run
     res = drain(srv, len(reqs))
-    assert srv.pending() == 0
+    assert srv.pending() == 0 and len(res) == len(reqs)
+    assert sorted(r["tag"] for r in res) == list(range(len(reqs)))
     for r in res:
         gi, k = reqs[r["tag"]]
         assert r["status"] == 0, r
-        assert r["count"] == plain[(gi, k)], (gi, k)
+        assert r["count"] == want[(gi, k)], (gi, k)
         assert r["t_submit_ns"] <= r["t_admit_ns"] <= r["t_done_ns"]
+    # the same requests as plain counts give the same values
+    for gi, k in sorted(set(reqs)):
+        assert hs[gi].count(k) == want[(gi, k)], (gi, k)
+    srv.close()
+
+
+def test_served_triangles_on_a_fresh_graph_of_outdegree_two(citron_gpu):
+    """Disjoint triangles: the DAG's largest out-degree is 2, so k = 3 is the
+    largest k with cliques.  A handle served before any plain count must
+    still give the triangle count."""
+    g = gg.disjoint_cliques([3] * 7)
+    h = citron_gpu.Graph.from_csr(g.row_ptr, g.col).order()
+    assert h.info()["max_outdeg"] == 2
+    srv = citron_gpu.Server(hbm_budget_bytes=1 << 20, max_slots=4)
+    gid = srv.add_graph(h)
+    for k in (1, 2, 3, 4):
+        srv.submit(gid, k, k)
+    res = {r["tag"]: r for r in drain(srv, 4)}
+    assert [res[k]["count"] for k in (1, 2, 3, 4)] == [21, 21, 7, 0]
+    assert all(res[k]["status"] == 0 for k in (1, 2, 3, 4))
     srv.close()
 
 
 def test_alone_equals_mix(citron_gpu, graphs):
-    hs, plain = graphs
+    hs, want = graphs
     srv = citron_gpu.Server(hbm_budget_bytes=1 << 30, max_slots=8)
     ids = [srv.add_graph(h) for h in hs]
     srv.submit(ids[2], 6, 0)
@@ -62,12 +104,12 @@ def test_alone_equals_mix(citron_gpu, graphs):
     srv.submit(ids[2], 6, 99)
     res = drain(srv, 30)
     mixed = [r["count"] for r in res if r["tag"] == 99][0]
-    assert alone == mixed == plain[(2, 6)]
+    assert alone == mixed == want[(2, 6)]
     srv.close()
 
 
 def test_small_budget_queues_instead_of_failing(citron_gpu, graphs):
-    hs, plain = graphs
+    hs, want = graphs
     # room for one request at a time (a request holds a few hundred bytes):
     # the rest wait in the queue
     srv = citron_gpu.Server(hbm_budget_bytes=300, max_slots=4)
@@ -77,7 +119,7 @@ def test_small_budget_queues_instead_of_failing(citron_gpu, graphs):
     res = drain(srv, 12)
     for r in res:
         assert r["status"] == 0
-        assert r["count"] == plain[(r["tag"] % 3, 5)]
+        assert r["count"] == want[(r["tag"] % 3, 5)]
     srv.close()
 
 

@@ -317,6 +317,66 @@ def test_check_csr_rejects_defects():
     assert not oracle.check_csr(g.n, g.row_ptr, bad)
 
 
+def _csr(n, rows):
+    rp = np.zeros(n + 1, np.int32)
+    for u in range(n):
+        rp[u + 1] = rp[u] + len(rows[u])
+    col = np.array([v for u in range(n) for v in rows[u]], np.int32)
+    return rp, col
+
+
+def test_check_csr_rejects_every_kind_of_defect():
+    # a path 0-1-2 plus the edge 2-3: valid as given
+    good = [[1], [0, 2], [1, 3], [2]]
+    rp, col = _csr(4, good)
+    assert oracle.check_csr(4, rp, col)
+    # asymmetric: 3 lists 2, but 2 does not list 3
+    rp, col = _csr(4, [[1], [0, 2], [1], [2]])
+    assert not oracle.check_csr(4, rp, col)
+    # column id out of range, above n - 1 and negative
+    rp, col = _csr(4, [[1], [0, 2], [1, 4], [2]])
+    assert not oracle.check_csr(4, rp, col)
+    rp, col = _csr(4, [[-1, 1], [0, 2], [1, 3], [2]])
+    assert not oracle.check_csr(4, rp, col)
+    # duplicate entry (a multi-edge listed twice in both rows)
+    rp, col = _csr(4, [[1, 1], [0, 0, 2], [1, 3], [2]])
+    assert not oracle.check_csr(4, rp, col)
+    # row_ptr not starting at 0, and decreasing
+    rp, col = _csr(4, good)
+    bad = rp.copy()
+    bad[0] = 1
+    assert not oracle.check_csr(4, bad, col)
+    bad = rp.copy()
+    bad[2], bad[3] = bad[3], bad[2]
+    assert not oracle.check_csr(4, bad, col)
+    # the empty graph and isolated vertices are valid
+    rp, col = _csr(3, [[], [], []])
+    assert oracle.check_csr(3, rp, col)
+
+
+# ----------------------------------------------------------- counter width
+
+def test_overflow_flag_set_exactly_at_2_to_64():
+    """The counter width is not stated in the paper; the reading taken is
+    uint64 with a flag raised iff the exact total is >= 2^64.  K_20 has
+    C(20,5) = 15504 5-cliques: a start of 2^64 - 15504 must wrap to exactly
+    0 with the flag set, one less must end at 2^64 - 1 with the flag clear."""
+    g = gg.complete(20)
+    dptr, dcol = oracle.orient(g.n, g.row_ptr, g.col)
+    c5 = math.comb(20, 5)
+    assert oracle.count_dag(g.n, dptr, dcol, 5) == (c5, False)
+    assert oracle.count_dag(g.n, dptr, dcol, 5, base=2**64 - c5) == (0, True)
+    assert oracle.count_dag(g.n, dptr, dcol, 5, base=2**64 - c5 - 1) == (2**64 - 1, False)
+    # far beyond: the value is the total mod 2^64
+    assert oracle.count_dag(g.n, dptr, dcol, 5, base=2**64 - 1) == (c5 - 1, True)
+    # the flag does not depend on how the roots are split: both halves from
+    # the same near-full base, summed, reach the same verdict
+    h = g.n // 2
+    a = oracle.count_dag(g.n, dptr, dcol, 5, 0, h, base=2**64 - c5)
+    b = oracle.count_dag(g.n, dptr, dcol, 5, h, g.n)
+    assert (a[0] + b[0]) % 2**64 == 0 and not a[1] and a[0] + b[0] == 2**64
+
+
 # ------------------------------------------------------- a planted mistake
 
 def test_a_planted_mistake_is_caught():
@@ -462,6 +522,30 @@ def test_core_ordering_closed_forms(g, degeneracy):
     assert sorted(rank.tolist()) == list(range(g.n))
 
 
+def test_core_rank_tie_break_by_hand():
+    """Algorithm 1 on a 4-cycle 0-1-2-3-0 with a pendant vertex 4 at 2,
+    derived by hand (rank = removal position; among vertices of smallest
+    current degree the smallest id goes first):
+      degrees 0:2 1:2 2:3 3:2 4:1 -> remove 4 (degree 1); 2 drops to 2
+      all of 0..3 now have degree 2 -> remove 0 (smallest id); 1, 3 drop to 1
+      1 and 3 have degree 1 -> remove 1; 2 drops to 1
+      2 and 3 have degree 1 -> remove 2; 3 drops to 0
+      remove 3.
+    Ties by the largest id would remove 3 second, and ties by the first
+    vertex met in a degree bucket differ again, so the rank pins the rule."""
+    rp, col = _csr(5, [[1, 3], [0, 2], [1, 3, 4], [0, 2], [2]])
+    rank = oracle.core_rank(5, rp, col)
+    assert rank.tolist() == [1, 2, 3, 4, 0]
+    dptr, dcol = oracle.orient_rank(5, rp, col, rank)
+    outs = [dcol[dptr[u]:dptr[u + 1]].tolist() for u in range(5)]
+    assert outs == [[1, 3], [2], [3], [], [2]]
+    # K_4 minus an edge (0-3 missing): degrees 0:2 1:3 2:3 3:2; remove 0
+    # (tie with 3, smaller id); 1, 2 drop to 2; now 1, 2, 3 all at 2 ->
+    # remove 1; 2, 3 drop to 1 -> remove 2; then 3.
+    rp, col = _csr(4, [[1, 2], [0, 2, 3], [0, 1, 3], [1, 2]])
+    assert oracle.core_rank(4, rp, col).tolist() == [0, 1, 2, 3]
+
+
 def test_core_ordering_never_exceeds_the_degree_ordering():
     g = gg.rmat(12, 16, seed=5)
     core_mx, dptr, dcol = _core_outdeg(g)
@@ -486,3 +570,27 @@ def test_edge_rooted_listing():
                 for r in rows[starts[i]:starts[i + 1]]:
                     assert (r[0], r[1]) == (u, v)
                     assert all((deg[x], x) < (deg[y], y) for x, y in zip(r[:-1], r[1:]))
+
+
+# ------------------------------------------------- all-core timing wrapper
+
+def test_parallel_wrapper_equals_one_thread(tmp_path):
+    from oracle import parallel as opar
+    g = gg.rmat(10, 16, seed=12)
+    dptr, dcol = oracle.orient(g.n, g.row_ptr, g.col)
+    for k in (3, 5):
+        want = oracle.count_dag(g.n, dptr, dcol, k)
+        res = opar.count_classes(g.n, dptr, dcol, k, stride=7, workers=3)
+        assert (res["count"], res["overflow"]) == want
+        # a run stopped after some classes resumes from its checkpoint
+        ck = str(tmp_path / f"ck{k}.json")
+        part = opar.count_classes(g.n, dptr, dcol, k, stride=7, classes=[0, 3, 5], workers=2,
+                                  checkpoint=ck, graph_key=g.sha256())
+        assert part["classes"] == 3
+        res = opar.count_classes(g.n, dptr, dcol, k, stride=7, workers=2, checkpoint=ck,
+                                 graph_key=g.sha256())
+        assert (res["count"], res["overflow"]) == want
+        # a checkpoint of another graph or k is not reused
+        other = opar.count_classes(g.n, dptr, dcol, k + 1, stride=7, workers=2, checkpoint=ck,
+                                   graph_key=g.sha256())
+        assert other["count"] == oracle.count_dag(g.n, dptr, dcol, k + 1)[0]
