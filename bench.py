@@ -13,9 +13,22 @@ k-cliques for every k.  The reported value is edges/s: (number of k values x
 m) / step time, with m the number of undirected edges.  Per-k count times
 come from HIP events on the stream the kernels run on.
 
+Time budget: warm-up and timed steps stop once another step would end past
+--budget-s seconds after the process started (default 500 s, so that a
+run asked for many steps of a workload whose steps take tens of seconds
+still ends within a ten-minute limit); at least one step is always timed.
+The line reports the steps actually run and the ones asked for.
+
 Roofline of the dominant kernel (the count kernel): algorithmic int32 VALU
 lane-ops per launch (4 per 64-bit AND+popcount, one per j-clique for
 j = 3..k-1) over the mean launch time, against 256 CUs x 64 lanes x 2.4 GHz.
+Per k, the line also gives the HBM figure of the paper's merge-based
+subgraph construction: the algorithmic bytes of every arc that survives
+pruning over the count time, against 8 TB/s.
+
+The CPU baseline is the oracle on the host's cores (one process per core, at
+most 16, roots dealt by residue class) on a sample of the roots, for the
+smallest k of the step, run before the GPU is touched.
 
 Prints ONE JSON line.  Only N=1 is supported: this build targets one GPU.
 """
@@ -27,6 +40,7 @@ import os
 import sys
 import time
 
+T_PROCESS_START = time.monotonic()
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
@@ -49,26 +63,42 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def cpu_baseline(g, k, budget_s=12.0):
-    """The oracle as it stands, single-threaded, on the roots v = 0 mod S of
-    the same graph, scaled by S to a whole-graph edges/s figure for k."""
+def cpu_baseline(g, k, budget_s=20.0, workers=None):
+    """The oracle as it stands on the host's cores (one process per core, at
+    most 16), each counting the roots of one residue class of a stride S
+    (roots v = r mod S, ids randomly permuted by the generator), for the
+    smallest k of the step: at larger k the oracle's time per root is
+    spread over many orders of magnitude (a hub vertex alone runs for
+    minutes), so no bounded sample estimates it.  The whole-graph time at
+    that core count is estimated as (sum of the class times) x (S /
+    classes) / cores.  S is chosen from a one-class probe so that the run
+    takes about budget_s seconds."""
     import oracle
+    from oracle import parallel as opar
+    workers = workers or min(16, os.cpu_count() or 1)
     dptr, dcol = oracle.orient(g.n, g.row_ptr, g.col)
-    stride = 65521
-    t = time.perf_counter()
-    oracle.count_dag(g.n, dptr, dcol, k, 0, g.n, stride)
-    dt = time.perf_counter() - t
-    # grow the sample toward the budget
-    while dt < budget_s / 8 and stride > 64:
-        stride = max(64, stride // 4)
+    # probe on one core, growing the sample until it takes a tenth of the
+    # budget (a few roots alone say little: their times are very uneven)
+    probe_stride = 1 << 16
+    while True:
         t = time.perf_counter()
-        oracle.count_dag(g.n, dptr, dcol, k, 0, g.n, stride)
-        dt = time.perf_counter() - t
-    est_full = dt * stride
-    return {"value": g.m / est_full, "unit": "edges/s", "cores": 1, "kind": "oracle",
-            "sample": f"k={k} only; roots v = 0 mod {stride} ({(g.n + stride - 1) // stride} of "
-                      f"{g.n} vertices, ids randomly permuted); {dt:.2f} s measured, scaled x{stride}",
-            "est_full_graph_s": est_full}
+        oracle.count_dag(g.n, dptr, dcol, k, 0, g.n, probe_stride)
+        t_probe = max(time.perf_counter() - t, 1e-6)
+        if t_probe >= budget_s / 10 or probe_stride <= 64:
+            break
+        probe_stride //= 4
+    # class time at stride S ~ t_probe * probe_stride / S, one class per worker
+    stride = int(min(probe_stride, max(workers, t_probe * probe_stride / budget_s)))
+    res = opar.count_classes(g.n, dptr, dcol, k, stride, classes=range(workers), workers=workers)
+    cpu = sum(res["class_seconds"])
+    est = cpu * (stride / workers) / workers
+    return {"value": g.m / est, "unit": "edges/s", "cores": workers, "kind": "oracle",
+            "k": k, "est_full_graph_s": est, "stride": stride, "cpu_s": cpu, "wall_s": res["wall_s"],
+            "sample": f"k = {k} only; roots v = r mod {stride} for r = 0..{workers - 1} "
+                      f"({workers} of {stride} residue classes, ids randomly permuted), one process per "
+                      f"class on {workers} host cores, {res['wall_s']:.1f} s wall, {cpu:.1f} s of CPU; "
+                      f"whole-graph time at {workers} cores estimated as the class CPU time "
+                      f"x {stride} / {workers} / {workers} = {est:.1f} s"}
 
 
 def kernel_digest(path):
@@ -106,6 +136,33 @@ def traffic_per_launch(ks):
         return float(rec["HBM bytes per launch"])
     except (KeyError, ValueError):
         return None
+
+
+def load_golden(name):
+    """The stored oracle values of a configuration graph (tests/golden), or
+    None.  Written by tests/golden/make_golden.py, which calls only the
+    oracle."""
+    path = os.path.join(ROOT, "tests", "golden", f"{name}.json")
+    try:
+        with open(path) as f:
+            return json.load(f)
+    except OSError:
+        return None
+
+
+def alg_bytes(gold, k):
+    """Algorithmic HBM bytes of one k-clique count under the paper's
+    merge-based subgraph construction (Algorithm 5 per arc, no reuse): for
+    every arc u -> v that survives pruning (|C_uv| >= k - 2), the two
+    out-lists 4 (d(u) + d(v)), the candidates' out-lists 4 sum_{w in C_uv}
+    d(w), and the compact output 8 (|C_uv| + 1).  From the oracle's stored
+    per-arc statistics; None when they are not stored for this k."""
+    if not gold:
+        return None
+    st = gold.get("work_model", {}).get(str(k))
+    if not st:
+        return None
+    return float(4 * st["kept_sum_duv"] + 4 * st["kept_sum_dw"] + 8 * (st["kept_sum_s"] + st["arcs_kept"]))
 
 
 def run_batch(args, citron, gg, torch, graphs):
@@ -279,6 +336,11 @@ def main():
     ap.add_argument("--workload", default="rmat20")
     ap.add_argument("--ks", type=int, nargs="+", default=[5, 6, 7])
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-budget-s", type=float, default=20.0,
+                    help="seconds of host wall time the CPU baseline aims for")
+    ap.add_argument("--budget-s", type=float, default=500.0,
+                    help="warm-up and timed steps stop when another step would end later than "
+                         "this many seconds after the process started (at least one step is timed)")
     ap.add_argument("--part-range", type=int, nargs=2, default=None,
                     help="with --parts: run only shares LO..HI-1 (a long count split over "
                          "several runs; the line then reports those shares)")
@@ -326,6 +388,31 @@ def main():
         log(f"generated {len(pre)} graphs, m = {sum(x.m for x in pre)} in "
             f"{time.perf_counter() - t:.1f} s")
 
+    if args.form in ("batch", "serve"):
+        import torch
+        import paper_2112_10913_amd as citron
+
+        torch.cuda.set_device(0)
+        # load the device code objects once (not a step: a tiny graph)
+        tiny = gg.rmat(8, 8, seed=1)
+        citron.Graph.from_csr(tiny.row_ptr, tiny.col).order().count(4)
+        torch.cuda.synchronize()
+        if args.form == "batch":
+            return run_batch(args, citron, gg, torch, pre)
+        return run_serve(args, citron, gg, torch)
+    t = time.perf_counter()
+    g = gg.config_graph(args.workload)
+    log(f"generated {args.workload}: n={g.n} m={g.m} in {time.perf_counter() - t:.1f} s")
+    gold = load_golden(args.workload)
+    cpu = None
+    if not args.no_cpu_baseline and not args.parts > 1:
+        # before the GPU is touched: worker processes fork from a process
+        # without device state, and the host is otherwise idle
+        log("cpu baseline (oracle, all host cores, sampled roots)")
+        t = time.perf_counter()
+        cpu = cpu_baseline(g, min(args.ks), budget_s=args.cpu_budget_s)
+        log(f"  {cpu['value']:.4g} edges/s on {cpu['cores']} cores ({time.perf_counter() - t:.1f} s)")
+
     import torch
     import paper_2112_10913_amd as citron
 
@@ -334,20 +421,13 @@ def main():
     tiny = gg.rmat(8, 8, seed=1)
     citron.Graph.from_csr(tiny.row_ptr, tiny.col).order().count(4)
     torch.cuda.synchronize()
-    if args.form == "batch":
-        return run_batch(args, citron, gg, torch, pre)
-    if args.form == "serve":
-        return run_serve(args, citron, gg, torch)
-    t = time.perf_counter()
-    g = gg.config_graph(args.workload)
-    log(f"generated {args.workload}: n={g.n} m={g.m} in {time.perf_counter() - t:.1f} s")
     rp = torch.from_numpy(g.row_ptr).cuda()
     col = torch.from_numpy(g.col).cuda()
     torch.cuda.synchronize()
 
     shares = {}
 
-    def step(record):
+    def step():
         ev = {}
         e0 = torch.cuda.Event(enable_timing=True)
         e1 = torch.cuda.Event(enable_timing=True)
@@ -388,28 +468,47 @@ def main():
                 f"{a.elapsed_time(b):.1f} ms")
         return h, counts, ev
 
+    def elapsed():
+        return time.monotonic() - T_PROCESS_START
+
+    warm_done, t_step = 0, None
     for i in range(args.warmup):
+        # after the first warm-up step (code paths and allocations warmed),
+        # further ones run only while the budget still holds every step asked for
+        if t_step is not None and elapsed() + (args.warmup - i + args.steps) * t_step > args.budget_s:
+            log(f"warm-up stops after {warm_done} of {args.warmup} steps (time budget)")
+            break
         log(f"warmup step {i + 1}/{args.warmup}")
-        h, _, _ = step(True)
+        t = time.perf_counter()
+        h, _, _ = step()
+        torch.cuda.synchronize()
+        t_step = time.perf_counter() - t
         h.free()
+        warm_done += 1
     torch.cuda.synchronize()
     per_k_ms = {k: [] for k in args.ks}
     order_ms = []
-    t0 = time.perf_counter()
     results = None
+    h = None
+    steps_done = 0
+    t0 = time.perf_counter()
     for i in range(args.steps):
+        if steps_done > 0 and elapsed() + (time.perf_counter() - t0) / steps_done > args.budget_s:
+            log(f"timed steps stop after {steps_done} of {args.steps} (time budget)")
+            break
         log(f"timed step {i + 1}/{args.steps}")
-        h, counts, ev = step(i == 0)
+        if h is not None:
+            h.free()
+        h, counts, ev = step()
         torch.cuda.synchronize()
         order_ms.append(ev["order"][0].elapsed_time(ev["order"][1]))
         for k in args.ks:
             per_k_ms[k].append(ev[k][0].elapsed_time(ev[k][1]))
         results = counts
-        if i < args.steps - 1:
-            h.free()
+        steps_done += 1
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    ms_per_step = wall * 1e3 / args.steps
+    ms_per_step = wall * 1e3 / steps_done
     info = h.info()
     m = g.m
     value = len(args.ks) * m / (ms_per_step / 1e3)
@@ -420,6 +519,8 @@ def main():
         per_k[str(k)] = {"count": results[k][0], "overflow": results[k][1],
                          "t_count_ms_mean": t_ms, "t_count_ms_median": float(np.median(per_k_ms[k])),
                          "edges_per_s": m / (t_ms / 1e3)}
+        if gold and str(k) in gold.get("counts", {}):
+            per_k[str(k)]["equals_oracle"] = (results[k][0] == gold["counts"][str(k)]["count"])
 
     # Algorithmic work of a count (Section III, Algorithm 2 with the
     # degrees-only last level): one 64-bit AND (+ popcount on the last
@@ -437,7 +538,15 @@ def main():
     tot_ops, tot_ms = 0, 0.0
     for k in args.ks:
         words = int(sum(cj[j] for j in range(3, k)) * frac_run)
+        t_s = per_k[str(k)]["t_count_ms_mean"] / 1e3
         per_k[str(k)]["alg_word_ops"] = words
+        per_k[str(k)]["valu"] = {"achieved_Tops": OPS_PER_WORD * words / t_s / 1e12,
+                                 "frac": OPS_PER_WORD * words / t_s / 1e12 / PEAK_VALU_TOPS}
+        hb = alg_bytes(gold, k)
+        if hb is not None:
+            hb *= frac_run
+            per_k[str(k)]["hbm"] = {"alg_bytes": hb, "achieved_GBps": hb / t_s / 1e9,
+                                    "frac": hb / t_s / 1e9 / PEAK_HBM_GBS}
         tot_ops += OPS_PER_WORD * words
         tot_ms += per_k[str(k)]["t_count_ms_mean"]
     achieved = tot_ops / (tot_ms / 1e3) / 1e12
@@ -446,21 +555,20 @@ def main():
                 "kernel": "count_kernel",
                 "algorithmic_unit": "int32 VALU lane-ops: 4 per 64-bit AND+popcount, one per j-clique, "
                                     "j = 3..k-1",
-                "launch_ms_mean": tot_ms / len(args.ks)}
+                "launch_ms_mean": tot_ms / len(args.ks),
+                "hbm_model": "per k: bytes of the merge-based subgraph construction over every arc with "
+                             "|C_uv| >= k-2, 4(d(u)+d(v)) + 4 sum_{w in C_uv} d(w) + 8(|C_uv|+1), "
+                             "over the count time, against 8 TB/s (per_k[k].hbm)"}
     if args.stats:
         # instrumented launches (not timed): the kernel's own word operations
         for k in args.ks:
             log(f"  work counters k={k}")
             per_k[str(k)]["work"] = h.work_stats(k)
 
-    cpu = None
-    if not args.no_cpu_baseline:
-        log("cpu baseline (oracle, sampled)")
-        cpu = cpu_baseline(g, min(args.ks))
-
     line = {
         "metric": "k-clique count time & edges/s per (graph,k); batched/served vs plain; p99 lat",
-        "value": value, "unit": "edges/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "value": value, "unit": "edges/s", "n_gpus": 1, "steps": steps_done, "warmup": warm_done,
+        "steps_requested": args.steps, "warmup_requested": args.warmup, "budget_s": args.budget_s,
         "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "u64", "data": "synthetic",
         "config": {"workload": f"{args.workload}: " + WORKLOADS.get(args.workload, args.workload),

@@ -379,6 +379,29 @@ def _batch_member(args):
     return g
 
 
+def batch_suite_member(i: int, seed0: int = 4000, scale_max: int = 16) -> CSR:
+    """Graph i of the mixed batch (before the shuffle of batch_suite)."""
+    return _batch_member((i, seed0, scale_max))
+
+
+def batch_suite_specs(count: int = 512, seed0: int = 4000, scale_max: int = 16) -> list:
+    """(kind, size) of every member without generating it: ("rmat", scale)
+    or ("er", n), indexed like batch_suite_member."""
+    out = []
+    for i in range(count):
+        rng = np.random.default_rng(seed0 + i)
+        if i % 2 == 0:
+            out.append(("rmat", int(rng.integers(8, scale_max + 1))))
+        else:
+            out.append(("er", int(rng.integers(1000, 50001))))
+    return out
+
+
+def batch_suite_order(count: int = 512, seed0: int = 4000) -> list:
+    """Member index at each position of batch_suite's shuffled list."""
+    return [int(j) for j in np.random.default_rng(seed0).permutation(count)]
+
+
 def batch_suite(count: int = 512, seed0: int = 4000, scale_max: int = 16, workers: int = 1) -> list:
     """Mixed batch of graphs: half R-MAT (scale U{8..scale_max}, edge factor
     U{8..32}), half Erdos-Renyi (n U[1000, 50000], mean degree U[10, 40]),
@@ -391,8 +414,7 @@ def batch_suite(count: int = 512, seed0: int = 4000, scale_max: int = 16, worker
             out = pool.map(_batch_member, jobs, chunksize=4)
     else:
         out = [_batch_member(j) for j in jobs]
-    order = np.random.default_rng(seed0).permutation(count)
-    return [out[j] for j in order]
+    return [out[j] for j in batch_suite_order(count, seed0)]
 
 
 def serve_suite(count: int = 64, seed0: int = 5000, scale_min: int = 12, scale_max: int = 20,

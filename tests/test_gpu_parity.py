@@ -273,11 +273,15 @@ def test_rmat20_per_arc_full_launch(citron_gpu):
     dptr, dcol = h.dag()
     src = np.repeat(np.arange(g.n), np.diff(dptr))
     assert list(src[idx]) == gold["arcs"]["u"] and list(dcol[idx]) == gold["arcs"]["v"]
-    for k in (5, 6):
+    for k in (5, 6, 7):
         say("rmat20 per-arc k", k)
         total, per_arc = h.count_per_arc(k)
-        assert int(per_arc.sum(dtype=np.uint64)) == total
+        assert int(per_arc.sum(dtype=np.uint64)) % 2**64 == total
         assert [int(x) for x in per_arc[idx]] == gold["arcs"][str(k)], k
+        # the launch the benchmark times (no per-arc output) gives the same
+        # whole count as the per-arc launch checked above
+        say("rmat20 whole-count launch k", k)
+        assert h.count(k) == total, k
 
 
 @pytest.mark.parametrize("k", [5, 6, 7, 8])
@@ -319,10 +323,12 @@ def test_chunglu22_counts(citron_gpu):
 def test_chunglu22_per_arc_full_launch(citron_gpu):
     g, gold, h = _chunglu22(citron_gpu)
     idx = np.array(gold["arcs"]["index"])
-    say("chunglu22 per-arc k 5")
-    total, per_arc = h.count_per_arc(5)
-    assert int(per_arc.sum(dtype=np.uint64)) == total
-    assert [int(x) for x in per_arc[idx]] == gold["arcs"]["5"]
+    for k in (5, 6, 7):
+        say("chunglu22 per-arc k", k)
+        total, per_arc = h.count_per_arc(k)
+        assert int(per_arc.sum(dtype=np.uint64)) % 2**64 == total
+        assert [int(x) for x in per_arc[idx]] == gold["arcs"][str(k)], k
+        assert h.count(k) == total, k
 
 
 @pytest.mark.parametrize("k", [5, 6, 7, 8, 9])

@@ -179,8 +179,17 @@ def test_autotune_picks_the_fastest_caches_it_and_rejects_changed_counts(tmp_pat
 def test_cpu_baseline_line():
     b = _bench()
     g = gg.rmat(12, 16, seed=5)
-    cb = b.cpu_baseline(g, 4, budget_s=0.4)
+    cb = b.cpu_baseline(g, 4, budget_s=0.5, workers=3)
     assert set(cb) >= {"value", "unit", "cores", "kind", "sample"}
-    assert cb["kind"] == "oracle" and cb["cores"] == 1 and cb["unit"] == "edges/s"
-    assert cb["value"] > 0 and "mod" in cb["sample"]
+    assert cb["kind"] == "oracle" and cb["cores"] == 3 and cb["unit"] == "edges/s"
+    assert cb["value"] > 0 and "mod" in cb["sample"] and cb["stride"] >= 3
     assert abs(cb["value"] * cb["est_full_graph_s"] - g.m) < 1e-6 * g.m
+
+
+def test_alg_bytes_model():
+    b = _bench()
+    gold = {"work_model": {"5": {"kept_sum_duv": 10, "kept_sum_dw": 20, "kept_sum_s": 3, "arcs_kept": 2}}}
+    assert b.alg_bytes(gold, 5) == 4 * 10 + 4 * 20 + 8 * (3 + 2)
+    assert b.alg_bytes(gold, 6) is None and b.alg_bytes(None, 5) is None
+    # the stored R-MAT 20 model: 2.95e11 bytes at k = 5
+    assert abs(b.alg_bytes(b.load_golden("rmat20"), 5) - 2.953e11) < 1e9
