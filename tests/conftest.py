@@ -22,3 +22,18 @@ def citron_gpu():
     import paper_2112_10913_amd as citron
     citron.load_library()
     return citron
+
+
+@pytest.fixture
+def progress(request):
+    """print() that bypasses output capture, so that a long GPU test shows
+    its progress while it runs."""
+    capman = request.config.pluginmanager.getplugin("capturemanager")
+
+    def say(*a):
+        if capman is None:
+            print(*a, flush=True)
+            return
+        with capman.global_and_fixture_disabled():
+            print(*a, flush=True)
+    return say

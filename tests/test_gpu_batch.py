@@ -1,5 +1,11 @@
-"""Batched form: replays of the captured launch and the autotuner.  Every
-count must equal the plain count exactly."""
+"""Batched form: replays of the captured launch and the autotuner; the mixed
+512-graph suite checked against the oracle's stored counts on a subset of
+its members and against plain counts for the rest.  Every count must be
+exact."""
+import json
+import os
+import time
+
 import numpy as np
 import pytest
 
@@ -47,3 +53,48 @@ def test_autotune_keeps_counts(citron_gpu, queries, tmp_path):
     assert citron_gpu.count_batch(gs, ks, tuning=best) == plain
     again, rep2 = autotune(gs, ks, space=space, reps=1, cache_path=cache)
     assert rep2["cached"] and again == best
+
+
+def test_mixed_suite_of_512_graphs_against_the_oracle(citron_gpu, progress):
+    """The batched configuration: 512 graphs (R-MAT scale 8..16 with edge
+    factor 8..32, Erdos-Renyi with n 1k..50k and mean degree 10..40), every
+    graph at k = 3..7 and at k = 8 except the R-MAT graphs of scale 15 and 16
+    (their k = 8 counts take 345 s of the suite's 384 s as plain counts), in
+    one count_batch call.  The oracle's stored counts
+    (tests/golden/batch512.json, k = 3..8) pin a subset that spans both
+    families; the other queries must equal plain counts."""
+    with open(os.path.join(os.path.dirname(__file__), "golden", "batch512.json")) as f:
+        gold = json.load(f)
+    graphs = gg.batch_suite(count=gold["suite"]["count"], seed0=gold["suite"]["seed0"], workers=8)
+    progress(f"  generated {len(graphs)} graphs")
+    hs = [citron_gpu.Graph.from_csr(g.row_ptr, g.col).order() for g in graphs]
+    progress("  loaded and ordered")
+    gs, ks, where = [], [], []
+    for i, (g, h) in enumerate(zip(graphs, hs)):
+        big = g.name.startswith(("rmat15", "rmat16"))
+        for k in range(3, 9):
+            if k == 8 and big:
+                continue
+            gs.append(h)
+            ks.append(k)
+            where.append((i, k))
+    t = time.perf_counter()
+    got = citron_gpu.count_batch(gs, ks)
+    progress(f"  batch of {len(ks)} queries: {time.perf_counter() - t:.1f} s")
+    pos = {m["position"]: m for m in gold["members"]}
+    checked = set()
+    for (i, k), c in zip(where, got):
+        if i in pos:
+            assert graphs[i].sha256() == pos[i]["sha256"]
+            assert c == pos[i]["counts"][str(k)]["count"], (graphs[i].name, k)
+            checked.add(i)
+    assert checked == set(pos)
+    kinds = {graphs[i].name[:2] for i in checked}
+    assert kinds == {"rm", "er"}
+    t = time.perf_counter()
+    plain = []
+    for j, (h, k) in enumerate(zip(gs, ks)):
+        plain.append(h.count(k))
+        if j % 500 == 499:
+            progress(f"  {j + 1} plain counts, {time.perf_counter() - t:.1f} s")
+    assert got == plain

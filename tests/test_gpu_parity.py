@@ -266,7 +266,7 @@ def test_rmat20_counts(citron_gpu):
         assert h.count(int(k)) == rec["count"]
 
 
-def test_rmat20_per_arc_full_launch(citron_gpu):
+def test_rmat20_per_arc_full_launch(citron_gpu, progress):
     """Full-size per-arc counts (the whole-graph launch) at the sampled arcs."""
     g, gold, h = _rmat20(citron_gpu)
     idx = np.array(gold["arcs"]["index"])
@@ -274,13 +274,13 @@ def test_rmat20_per_arc_full_launch(citron_gpu):
     src = np.repeat(np.arange(g.n), np.diff(dptr))
     assert list(src[idx]) == gold["arcs"]["u"] and list(dcol[idx]) == gold["arcs"]["v"]
     for k in (5, 6, 7):
-        say("rmat20 per-arc k", k)
+        progress(f"  rmat20 per-arc launch k={k}")
         total, per_arc = h.count_per_arc(k)
         assert int(per_arc.sum(dtype=np.uint64)) % 2**64 == total
         assert [int(x) for x in per_arc[idx]] == gold["arcs"][str(k)], k
         # the launch the benchmark times (no per-arc output) gives the same
         # whole count as the per-arc launch checked above
-        say("rmat20 whole-count launch k", k)
+        progress(f"  rmat20 whole-count launch k={k}")
         assert h.count(k) == total, k
 
 
@@ -320,11 +320,11 @@ def test_chunglu22_counts(citron_gpu):
         assert h.count(int(k)) == rec["count"]
 
 
-def test_chunglu22_per_arc_full_launch(citron_gpu):
+def test_chunglu22_per_arc_full_launch(citron_gpu, progress):
     g, gold, h = _chunglu22(citron_gpu)
     idx = np.array(gold["arcs"]["index"])
     for k in (5, 6, 7):
-        say("chunglu22 per-arc k", k)
+        progress(f"  chunglu22 per-arc launch k={k}")
         total, per_arc = h.count_per_arc(k)
         assert int(per_arc.sum(dtype=np.uint64)) % 2**64 == total
         assert [int(x) for x in per_arc[idx]] == gold["arcs"][str(k)], k
