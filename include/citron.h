@@ -266,6 +266,28 @@ int32_t citron_server_poll(citron_server* s, citron_result* results, int32_t max
 int32_t citron_server_pending(citron_server* s);
 void citron_server_destroy(citron_server* s);
 
+/* ------------------------------------------------- no-allocation path */
+
+/* The ordering phase for callers that cannot allocate device memory: code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc.  Same result as citron_load_csr + citron_order +
+ * citron_get_dag, written into the caller's device buffers:
+ *   n, nnz, row_ptr, col_idx  a device CSR as for citron_load_csr (device
+ *            pointers, validated on the device by the same rules; EINVAL
+ *            on a violation); 0 <= n <= 2^22
+ *   dag_ptr  device int32[n+1], dag_col device int32[nnz/2]: the DAG in the
+ *            order of citron_get_dag
+ *   max_outdeg  host int32: the largest out-degree
+ *   stream   hipStream_t (NULL = default); the call synchronises it
+ * Working memory (out-degrees, scan partial sums, flags) is one static
+ * device array of about 16.8 MB per device, held until the process ends;
+ * no hipMalloc, hipFree or allocating library routine is called.  Calls
+ * on one device are serialised by the library (they would otherwise race
+ * on the shared array); n above 2^22 gives CITRON_EINVAL. */
+citron_status citron_order_noalloc(int32_t n, int64_t nnz, const int32_t* row_ptr,
+                                   const int32_t* col_idx, int32_t* dag_ptr, int32_t* dag_col,
+                                   int32_t* max_outdeg, void* stream);
+
 /* ------------------------------------------------------------ testing */
 
 /* Test hook: the next count on g starts its accumulator at `base` instead

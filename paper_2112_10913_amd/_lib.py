@@ -134,6 +134,8 @@ def load_library():
     lib.citron_server_pending.restype = ctypes.c_int32
     lib.citron_server_destroy.argtypes = [vp]
     lib.citron_server_destroy.restype = None
+    lib.citron_order_noalloc.argtypes = [ctypes.c_int32, ctypes.c_int64, vp, vp, vp, vp, _i32p, vp]
+    lib.citron_order_noalloc.restype = ctypes.c_int32
     lib.citron_test_seed_accumulator.argtypes = [vp, ctypes.c_uint64]
     lib.citron_test_seed_accumulator.restype = ctypes.c_int32
     _lib = lib
@@ -338,6 +340,29 @@ class Graph:
             self.free()
         except Exception:
             pass
+
+
+def order_noalloc(row_ptr, col, dag_ptr, dag_col, stream=None) -> int:
+    """citron_order_noalloc: the degree-ordered DAG of a device CSR written
+    into the device tensors dag_ptr (int32[n+1]) and dag_col (int32[m]),
+    with no device allocation; returns the largest out-degree."""
+    lib = load_library()
+    torch = _torch()
+    for t in (row_ptr, col, dag_ptr, dag_col):
+        if not (t.is_cuda and t.dtype == torch.int32 and t.is_contiguous()):
+            raise ValueError("order_noalloc takes contiguous int32 device tensors")
+    n = row_ptr.numel() - 1
+    nnz = col.numel()
+    if dag_ptr.numel() < n + 1 or dag_col.numel() < nnz // 2:
+        raise ValueError("dag_ptr needs n+1 entries and dag_col nnz/2")
+    s = ctypes.c_void_p(stream.cuda_stream) if stream is not None else _current_stream()
+    mx = ctypes.c_int32(-1)
+    st = lib.citron_order_noalloc(n, nnz, row_ptr.data_ptr(), col.data_ptr() if nnz else None,
+                                  dag_ptr.data_ptr(), dag_col.data_ptr() if nnz else None,
+                                  ctypes.byref(mx), s)
+    if st:
+        raise _err(st)
+    return mx.value
 
 
 def count_batch(graphs, ks, tuning: Tuning | None = None, return_status: bool = False):

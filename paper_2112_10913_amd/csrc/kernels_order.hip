@@ -199,7 +199,8 @@ __global__ void orient_count_kernel(int32_t n, const int32_t* __restrict__ row_p
 // Place the kept neighbours (second loop of Algorithm 3).  One wavefront per
 // vertex walks its row in 64-entry steps; a ballot marks the kept entries and
 // each lane writes at the count of kept entries before it, so the row keeps
-// its ascending order.  dag_src receives the source vertex of every arc.
+// its ascending order.  dag_src (may be null) receives the source vertex of
+// every arc.
 __global__ void orient_scatter_kernel(int32_t n, const int32_t* __restrict__ row_ptr,
                                       const int32_t* __restrict__ col,
                                       const int32_t* __restrict__ dag_ptr,
@@ -224,7 +225,7 @@ __global__ void orient_scatter_kernel(int32_t n, const int32_t* __restrict__ row
         if (keep) {
             const int32_t pos = out + __popcll(mask & below);
             dag_col[pos] = v;
-            dag_src[pos] = (int32_t)u;
+            if (dag_src) dag_src[pos] = (int32_t)u;
         }
         out += __popcll(mask);
     }
