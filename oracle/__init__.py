@@ -55,6 +55,7 @@ def _load():
                                          _u64p, _u64p]
         lib.oracle_core_rank.argtypes = [ctypes.c_int32, _i32p, _i32p, _i32p]
         lib.oracle_orient_rank.argtypes = [ctypes.c_int32, _i32p, _i32p, _i32p, _i32p, _i32p]
+        lib.oracle_peel_rounds.argtypes = [ctypes.c_int32, _i32p, _i32p, _i32p]
         lib.oracle_list_arcs.argtypes = [ctypes.c_int32, _i32p, _i32p, ctypes.c_int32,
                                          _i32p, _i32p, ctypes.c_int64, _u64p, _i32p,
                                          ctypes.c_uint64, _u64p]
@@ -199,6 +200,31 @@ def orient_rank(n, row_ptr, col, rank):
     dcol = np.zeros(max(m, 1), np.int32)
     _check(_load().oracle_orient_rank(n, pa, pb, pr, dptr.ctypes.data_as(_i32p), dcol.ctypes.data_as(_i32p)))
     return dptr, dcol[:m]
+
+
+def peel_rounds(n, row_ptr, col):
+    """Round in which each vertex leaves the level-synchronous peeling
+    (the parallel form of the core ordering)."""
+    a, pa = _i32(row_ptr)
+    b, pb = _i32(col if len(col) else np.zeros(1, np.int32))
+    rnd = np.zeros(max(n, 1), np.int32)
+    _check(_load().oracle_peel_rounds(n, pa, pb, rnd.ctypes.data_as(_i32p)))
+    return rnd[:n]
+
+
+def peel_rank(n, row_ptr, col):
+    """Total order of the peeling: position of each vertex when sorted by
+    (round, id)."""
+    rnd = peel_rounds(n, row_ptr, col)
+    order = np.lexsort((np.arange(n), rnd))
+    rank = np.empty(n, np.int32)
+    rank[order] = np.arange(n, dtype=np.int32)
+    return rank
+
+
+def orient_peel(g):
+    """The DAG of the level-synchronous peeling of graph g."""
+    return orient_rank(g.n, g.row_ptr, g.col, peel_rank(g.n, g.row_ptr, g.col))
 
 
 def orient_core(g):

@@ -577,3 +577,57 @@ int oracle_orient_rank(int32_t n, const int32_t* row_ptr, const int32_t* col, co
     }
     return ORACLE_OK;
 }
+
+/* --------------------------- level-synchronous core ordering (peeling) */
+
+/* A parallel form of the core ordering: Algorithm 1 removes one vertex of
+ * smallest current degree at a time, which the paper calls inherently
+ * sequential; here every vertex whose current degree is at most a
+ * threshold t leaves in the same round.  t starts at the smallest degree;
+ * a round removes the set F = {present v : deg(v) <= t} at once and then
+ * lowers the degrees of the neighbours still present; when F is empty, t
+ * rises to the smallest degree still present.  round[v] receives the round
+ * in which v left.  Ordering vertices by (round, id) and directing every
+ * edge from the earlier to the later vertex bounds each out-degree by the
+ * degree the vertex had when it left, which is at most t, and t never
+ * exceeds the degeneracy: the largest out-degree is the degeneracy, as for
+ * Algorithm 1.  Written as the plain sequence of rounds. */
+int oracle_peel_rounds(int32_t n, const int32_t* row_ptr, const int32_t* col, int32_t* round)
+{
+    if (n < 0) return ORACLE_EINVAL;
+    int32_t* deg = (int32_t*)malloc(sizeof(int32_t) * ((size_t)n + 1));
+    int32_t* frontier = (int32_t*)malloc(sizeof(int32_t) * ((size_t)n + 1));
+    if (!deg || !frontier) { free(deg); free(frontier); return ORACLE_ENOMEM; }
+    int32_t remaining = n, t = 0, r = 0;
+    for (int32_t v = 0; v < n; ++v) {
+        deg[v] = (int32_t)(row_ptr[v + 1] - row_ptr[v]);
+        round[v] = -1;
+    }
+    while (remaining > 0) {
+        /* the vertices present with degree <= t */
+        int32_t nf = 0;
+        for (int32_t v = 0; v < n; ++v)
+            if (round[v] < 0 && deg[v] <= t) frontier[nf++] = v;
+        if (nf == 0) {
+            /* raise t to the smallest degree present */
+            int32_t mn = -1;
+            for (int32_t v = 0; v < n; ++v)
+                if (round[v] < 0 && (mn < 0 || deg[v] < mn)) mn = deg[v];
+            t = mn;
+            continue;
+        }
+        /* they leave together ... */
+        for (int32_t i = 0; i < nf; ++i) round[frontier[i]] = r;
+        /* ... and their neighbours still present lose one degree per edge */
+        for (int32_t i = 0; i < nf; ++i) {
+            int32_t v = frontier[i];
+            for (int64_t e = row_ptr[v]; e < row_ptr[v + 1]; ++e)
+                if (round[col[e]] < 0) deg[col[e]] -= 1;
+        }
+        remaining -= nf;
+        r += 1;
+    }
+    free(deg);
+    free(frontier);
+    return ORACLE_OK;
+}

@@ -546,6 +546,54 @@ def test_core_rank_tie_break_by_hand():
     assert oracle.core_rank(4, rp, col).tolist() == [0, 1, 2, 3]
 
 
+def test_peeling_rounds_by_hand():
+    """Level-synchronous peeling, derived by hand.
+    4-cycle 0-1-2-3-0 with a pendant 4 at 2: degrees 2,2,3,2,1; t = 1:
+    round 0 removes {4} (2 drops to 2); no vertex is left at degree <= 1, so
+    t rises to 2 and round 1 removes {0, 1, 2, 3} together.
+    Path 0-1-2-3-4: degrees 1,2,2,2,1; t = 1: round 0 removes {0, 4}, 1 and
+    3 drop to 1; round 1 removes {1, 3}, 2 drops to 0; round 2 removes {2}.
+    (Algorithm 1 would remove the path's vertices in id order 0..4.)"""
+    rp, col = _csr(5, [[1, 3], [0, 2], [1, 3, 4], [0, 2], [2]])
+    assert oracle.peel_rounds(5, rp, col).tolist() == [1, 1, 1, 1, 0]
+    assert oracle.peel_rank(5, rp, col).tolist() == [1, 2, 3, 4, 0]
+    rp, col = _csr(5, [[1], [0, 2], [1, 3], [2, 4], [3]])
+    assert oracle.peel_rounds(5, rp, col).tolist() == [0, 1, 2, 1, 0]
+    assert oracle.core_rank(5, rp, col).tolist() == [0, 1, 2, 3, 4]
+    dptr, dcol = oracle.orient_rank(5, rp, col, oracle.peel_rank(5, rp, col))
+    assert [dcol[dptr[u]:dptr[u + 1]].tolist() for u in range(5)] == [[1], [2], [], [2], [3]]
+
+
+@pytest.mark.parametrize("seed", [10, 11])
+def test_peeling_reaches_the_degeneracy(seed):
+    for g in _random_graphs(5, 2, 12, seed):
+        dptr, dcol = oracle.orient_peel(g)
+        assert int(np.diff(dptr).max(initial=0)) == _brute_degeneracy(g), g.n
+        assert int(dptr[-1]) == g.m
+        for k in range(1, 7):
+            assert oracle.count_dag(g.n, dptr, dcol, k)[0] == brute_count(g, k), k
+
+
+@pytest.mark.parametrize("g,degeneracy", [
+    (gg.complete(12), 11), (gg.complete_bipartite(4, 9), 4), (gg.grid(5, 7), 2),
+    (gg.hypercube(5), 5), (gg.wheel(9), 3), (gg.paley(29), 14), (gg.turan(12, 4), 9),
+    (gg.empty(6), 0)])
+def test_peeling_closed_forms(g, degeneracy):
+    dptr, dcol = oracle.orient_peel(g)
+    assert int(np.diff(dptr).max(initial=0)) == degeneracy
+    # a regular graph leaves in one round: the order is then by id
+    if len(set(np.diff(g.row_ptr).tolist())) == 1 and g.n:
+        assert set(oracle.peel_rounds(g.n, g.row_ptr, g.col).tolist()) == {0}
+
+
+def test_peeling_matches_algorithm_1_maximum_outdegree():
+    g = gg.rmat(12, 16, seed=5)
+    core_mx = int(np.diff(oracle.orient_core(g)[0]).max())
+    dptr, dcol = oracle.orient_peel(g)
+    assert int(np.diff(dptr).max()) == core_mx
+    assert oracle.count_dag(g.n, dptr, dcol, 5)[0] == ocount(g, 5)
+
+
 def test_core_ordering_never_exceeds_the_degree_ordering():
     g = gg.rmat(12, 16, seed=5)
     core_mx, dptr, dcol = _core_outdeg(g)
