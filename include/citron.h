@@ -115,6 +115,30 @@ citron_status citron_load_csr(int32_t n, int64_t nnz, const int32_t* row_ptr,
  * the device.  LOADED -> ORDERED; calling it again is a no-op. */
 citron_status citron_order(citron_graph* g);
 
+/* Ordering phase with the core (degeneracy) ordering instead (Section III,
+ * Algorithm 1; the paper's Section IV explains why it gives the smallest
+ * largest out-degree and why it is sequential as written).  Algorithm 1
+ * removes one vertex of smallest current degree at a time; this call runs
+ * its level-synchronous form on the device: with a threshold t starting at
+ * the smallest degree, each round removes every vertex still present whose
+ * current degree is <= t, then lowers its neighbours' degrees; t rises to
+ * the smallest degree present when no vertex is left at or below it.
+ * Vertices are ordered by (round, id) and arcs go from earlier to later,
+ * so every out-degree is at most the degeneracy (the largest out-degree
+ * equals it, as with Algorithm 1), while the order itself may differ from
+ * Algorithm 1's one-at-a-time order.  Out-lists keep ascending id order.
+ * LOADED -> ORDERED; no-op if already ordered this way, CITRON_ESTATE if
+ * already ordered by degree.  Counts do not depend on the ordering; per-arc
+ * counts and citron_get_dag follow it. */
+citron_status citron_order_core(citron_graph* g);
+
+/* The order key of an ORDERED graph: key (host int32[n]) receives the
+ * degree of each vertex under the degree ordering, or the round in which it
+ * left the peeling under the core ordering (ties broken by id in both);
+ * *rounds (may be NULL) the number of peeling rounds (0 for the degree
+ * ordering). */
+citron_status citron_get_order_key(const citron_graph* g, int32_t* key, int32_t* rounds);
+
 /* Counting phase: number of k-cliques of the graph, 1 <= k <= CITRON_KMAX.
  * k = 1 gives n, k = 2 gives m.  Requires ORDERED (else CITRON_ESTATE).
  * Returns 0 on error; on CITRON_EOVERFLOW returns the count mod 2^64.
@@ -124,6 +148,15 @@ citron_status citron_order(citron_graph* g);
  * out-degree, reach 2^31 words; CITRON_ENOMEM if they do not fit in device
  * memory.  st may be NULL. */
 uint64_t citron_count(citron_graph* g, int32_t k, citron_status* st);
+
+/* The same count with the paper's own unit of work (Section III,
+ * Algorithm 2 run per vertex, the subgraph of Algorithm 5 built once per
+ * vertex): every vertex u with out-degree >= k - 1 is one work item whose
+ * search starts at u itself and walks u's arcs in turn, with no vertex or
+ * arc split across waves.  An ablation of the edge-rooted unit and the
+ * heavy-arc split of citron_count, which it must equal; arguments, errors
+ * and overflow as for citron_count (here k = 3 also runs the kernel). */
+uint64_t citron_count_vertex_rooted(citron_graph* g, int32_t k, citron_status* st);
 
 /* As citron_count, and also writes per_arc[e] = the number of k-cliques
  * whose two lowest vertices in the degree ordering are the endpoints of
@@ -168,7 +201,8 @@ citron_status citron_count_batch(citron_graph* const* gs, const int32_t* ks, int
                                  const citron_tuning* t);
 
 /* Copy the DAG to host memory: dag_ptr int32[n+1], dag_col int32[m], in
- * the arc order of Algorithm 3 (rows by source id, each row ascending). */
+ * the arc order of Algorithm 3 (rows by source id, each row ascending), for
+ * whichever ordering the graph was ordered by. */
 citron_status citron_get_dag(const citron_graph* g, int32_t* dag_ptr, int32_t* dag_col);
 
 /* Sizes of a graph.  Any output pointer may be NULL.  max_outdeg is -1

@@ -94,8 +94,14 @@ def load_library():
     lib.citron_load_csr.restype = ctypes.c_int32
     lib.citron_order.argtypes = [vp]
     lib.citron_order.restype = ctypes.c_int32
+    lib.citron_order_core.argtypes = [vp]
+    lib.citron_order_core.restype = ctypes.c_int32
+    lib.citron_get_order_key.argtypes = [vp, _i32p, _i32p]
+    lib.citron_get_order_key.restype = ctypes.c_int32
     lib.citron_count.argtypes = [vp, ctypes.c_int32, _i32p]
     lib.citron_count.restype = ctypes.c_uint64
+    lib.citron_count_vertex_rooted.argtypes = [vp, ctypes.c_int32, _i32p]
+    lib.citron_count_vertex_rooted.restype = ctypes.c_uint64
     lib.citron_count_per_arc.argtypes = [vp, ctypes.c_int32, vp, _i32p]
     lib.citron_count_per_arc.restype = ctypes.c_uint64
     lib.citron_count_part.argtypes = [vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, _i32p]
@@ -226,11 +232,30 @@ class Graph:
             raise CitronError(EINVAL, "graph has been freed")
         return self._h
 
-    def order(self) -> "Graph":
-        st = load_library().citron_order(self._handle())
+    def order(self, ordering: str = "degree") -> "Graph":
+        """The ordering phase: "degree" (Section IV, the default) or "core"
+        (the level-synchronous form of Algorithm 1's core ordering)."""
+        lib = load_library()
+        if ordering == "degree":
+            st = lib.citron_order(self._handle())
+        elif ordering == "core":
+            st = lib.citron_order_core(self._handle())
+        else:
+            raise ValueError("ordering must be 'degree' or 'core'")
         if st:
             raise _err(st)
         return self
+
+    def order_key(self) -> tuple[np.ndarray, int]:
+        """(per-vertex order key, number of peeling rounds): the degree under
+        the degree ordering, the peeling round under the core ordering."""
+        key = np.zeros(max(self.n, 1), np.int32)
+        rounds = ctypes.c_int32(0)
+        st = load_library().citron_get_order_key(self._handle(), key.ctypes.data_as(_i32p),
+                                                 ctypes.byref(rounds))
+        if st:
+            raise _err(st)
+        return key[:self.n], rounds.value
 
     def count_checked(self, k: int) -> tuple[int, bool]:
         """(count mod 2^64, overflowed)."""
@@ -246,6 +271,17 @@ class Graph:
         if ovf:
             raise CitronError(EOVERFLOW, "count is >= 2^64", v)
         return v
+
+    def count_vertex_rooted(self, k: int) -> int:
+        """The same count with the vertex-rooted unit (one work item per
+        vertex, no split): the ablation of the edge-rooted unit."""
+        st = ctypes.c_int32(0)
+        v = load_library().citron_count_vertex_rooted(self._handle(), int(k), ctypes.byref(st))
+        if st.value == EOVERFLOW:
+            raise CitronError(EOVERFLOW, "count is >= 2^64", int(v))
+        if st.value != OK:
+            raise _err(st.value)
+        return int(v)
 
     def count_per_arc(self, k: int):
         """(total, per-arc counts as a uint64 numpy array in DAG arc order)."""

@@ -126,6 +126,7 @@ static void free_graph_memory(citron_graph* g)
     dfree(g->d_dag_src);
     dfree(g->d_small);
     dfree(g->d_scan_ws);
+    dfree(g->d_key);
     dfree(g->d_query);
     dfree(g->d_scratch);
     dfree(g->d_stats);
@@ -139,6 +140,8 @@ static void free_graph_memory(citron_graph* g)
     for (int k = 0; k <= CITRON_KMAX; ++k) {
         dfree(g->d_buckets[k]);
         g->bucket_bytes[k] = 0;
+        dfree(g->d_vbuckets[k]);
+        g->vbucket_bytes[k] = 0;
     }
     g->rows_valid = false;
     free_plan(g);
@@ -334,7 +337,7 @@ citron_status ensure_buckets(citron_graph* g, int32_t k)
         tab.push_back((int32_t)items);
         tab.push_back(b.first);
         tab.push_back(b.cnt);
-        tab.push_back((b.key << 1) | b.light);
+        tab.push_back((b.key << 2) | (b.light ? kItemLightVertex : kItemHeavyArc));
         items += (int64_t)b.cnt * parts;
         if (items > 0x7fffffffLL) return fail(CITRON_EINVAL, "too many work items for one count");
     }
@@ -351,6 +354,47 @@ citron_status ensure_buckets(citron_graph* g, int32_t k)
     g->n_buckets[k] = nb;
     g->n_work[k] = (int32_t)items;
     g->bucket_split[k] = pct;
+    return CITRON_OK;
+}
+
+// Vertex-rooted schedule of a k-clique count (Algorithm 2's unit): every
+// vertex with out-degree >= k - 1 is one item, searched from its own root,
+// largest out-degree first; heavy vertices (out-degree > 64) by the heavy
+// engine, light ones as one light-engine unit each.  No vertex is split.
+citron_status ensure_vbuckets(citron_graph* g, int32_t k)
+{
+    if (g->d_vbuckets[k]) return CITRON_OK;
+    const int32_t D = std::max(g->max_outdeg, 2);
+    auto v_at_least = [&](int32_t x) -> int64_t {   // vertices with out-degree >= x
+        if (x > D) return 0;
+        if (x < 2) x = 2;
+        return g->h_vscan[(size_t)(D - x + 1)];
+    };
+    const int64_t n_heavy = v_at_least(kLightMaxDeg + 1);
+    std::vector<int32_t> tab;
+    int64_t items = 0;
+    for (int32_t d = D; d >= std::max(k - 1, 2); --d) {
+        const int64_t cnt = v_at_least(d) - v_at_least(d + 1);
+        if (cnt <= 0) continue;
+        const bool heavy = d > kLightMaxDeg;
+        tab.push_back((int32_t)items);
+        tab.push_back((int32_t)(heavy ? v_at_least(d + 1) : v_at_least(d + 1) - n_heavy));
+        tab.push_back((int32_t)cnt);
+        tab.push_back((d << 2) | (heavy ? kItemHeavyVertex : kItemLightRoot));
+        items += cnt;
+    }
+    const int32_t nb = (int32_t)(tab.size() / 4);
+    tab.push_back((int32_t)items);
+    tab.push_back(0);
+    tab.push_back(0);
+    tab.push_back(0);
+    citron_status st = dalloc(&g->d_vbuckets[k], tab.size(), &g->device_bytes, "vertex buckets");
+    if (st) return st;
+    g->vbucket_bytes[k] = (int64_t)(sizeof(int32_t) * tab.size());
+    hipError_t e = hipMemcpy(g->d_vbuckets[k], tab.data(), sizeof(int32_t) * tab.size(), hipMemcpyHostToDevice);
+    if (e != hipSuccess) return hip_fail(e, "vertex buckets");
+    g->n_vbuckets[k] = nb;
+    g->n_vwork[k] = (int32_t)items;
     return CITRON_OK;
 }
 
@@ -437,7 +481,8 @@ struct ListItems {
 // One query through the count kernel; synchronous on the graph's stream.
 static citron_status run_single(citron_graph* g, int32_t k, unsigned long long* per_arc, bool stats,
                                 uint64_t* out_count, const int32_t* arc_list = nullptr, int32_t n_list = 0,
-                                int32_t part = 0, int32_t nparts = 1, uint64_t* stats_out = nullptr)
+                                int32_t part = 0, int32_t nparts = 1, uint64_t* stats_out = nullptr,
+                                bool vertex_rooted = false)
 {
     std::lock_guard<std::mutex> lock(g->mu);
     hipError_t e = hipSetDevice(g->device);
@@ -448,18 +493,23 @@ static citron_status run_single(citron_graph* g, int32_t k, unsigned long long* 
     g->seed_pending = false;
     hipStream_t s = g->stream;
     if (stats) memset(g->h_small->stats, 0, sizeof(g->h_small->stats));
-    if (k == 3 && arc_list) {
+    if (vertex_rooted) {
+        // the vertex-rooted unit runs the kernel for every k >= 3 (no
+        // triangle shortcut: its k = 3 is the kernel's degrees-only level)
+        st = ensure_vbuckets(g, k);
+        if (st) return st;
+    } else if (k == 3 && arc_list) {
         e = launch_gather_arc_c(arc_list, n_list, g->d_arc_c, per_arc, s);
         if (e == hipSuccess) e = hipStreamSynchronize(s);
         if (e != hipSuccess) return hip_fail(e, "per-arc copy");
         *out_count = 0;   // the caller sums the listed arcs
         return CITRON_OK;
     }
-    if (k == 3 && part != 0) {   // a strided part of the triangle sum: all in part 0
+    if (!vertex_rooted && k == 3 && part != 0) {   // a strided part of the triangle sum: all in part 0
         *out_count = 0;
         return CITRON_OK;
     }
-    if (k == 3) {
+    if (!vertex_rooted && k == 3) {
         // triangles: the popcounts of the rows, summed by the build
         if (per_arc) {
             e = launch_arc_c_to_u64(g->m, g->d_arc_c, per_arc, s);
@@ -471,12 +521,17 @@ static citron_status run_single(citron_graph* g, int32_t k, unsigned long long* 
         if (g->tri_ovf || c < seed) return fail(CITRON_EOVERFLOW, "count is >= 2^64; value is mod 2^64");
         return CITRON_OK;
     }
-    st = ensure_buckets(g, k);
-    if (st) return st;
+    if (!vertex_rooted) {
+        st = ensure_buckets(g, k);
+        if (st) return st;
+    }
     const citron_tuning& t = g->tuning;
     const int wg = t.wg_waves;
     const int32_t blocks = device_cus(g->device) * t.blocks_per_cu;
-    const int64_t swords = count_scratch_words(g->max_outdeg, k, wg);
+    // a unit rooted at a vertex has one more level to choose than one rooted
+    // at an arc: its stacks are sized as for k + 1
+    const int32_t stack_k = vertex_rooted ? k + 1 : k;
+    const int64_t swords = count_scratch_words(g->max_outdeg, stack_k, wg);
     st = ensure_scratch(g, std::max<int64_t>(swords * 8 * blocks, 8));
     if (st) return st;
     if (stats && !g->d_stats) {
@@ -494,6 +549,13 @@ static citron_status run_single(citron_graph* g, int32_t k, unsigned long long* 
     if (per_arc && (e = launch_fill_u64(per_arc, 0, arc_list ? n_list : g->m, s)) != hipSuccess)
         return hip_fail(e, "fill");
     g->h_small->query = make_query(g, k, &sd->acc, &sd->overflow, per_arc, stats ? g->d_stats : nullptr, 0);
+    if (vertex_rooted) {
+        QueryDesc& q = g->h_small->query;
+        q.buckets = g->d_vbuckets[k];
+        q.n_buckets = g->n_vbuckets[k];
+        q.n_work = g->n_vwork[k];
+        q.n_items = q.n_work;
+    }
     ListItems li;
     if (nparts > 1) {
         // items part, part + nparts, part + 2 nparts, ... of the schedule
@@ -523,10 +585,10 @@ static citron_status run_single(citron_graph* g, int32_t k, unsigned long long* 
     cl.item_ctr = &sd->item_ctr;
     cl.scratch = g->d_scratch;
     cl.scratch_words = swords;
-    cl.max_k = k;
+    cl.max_k = stack_k;
     cl.blocks = blocks;
     cl.wg_waves = wg;
-    cl.lds_bytes = count_lds_bytes(0, k, wg);
+    cl.lds_bytes = count_lds_bytes(0, stack_k, wg);
     cl.flush_rows = t.flush_rows;
     cl.arc_lds_max = t.arc_lds_max;
     cl.stats = stats;
@@ -641,11 +703,81 @@ citron_status citron_load_csr(int32_t n, int64_t nnz, const int32_t* row_ptr, co
     return CITRON_OK;
 }
 
-citron_status citron_order(citron_graph* g)
+// Level-synchronous peeling (kernels_core.hip): g->d_key[v] = the round in
+// which v leaves.  Frontier buffers are temporary.
+static citron_status peel_key(citron_graph* g)
+{
+    hipStream_t s = g->stream;
+    int64_t* acct = &g->device_bytes;
+    citron_status st;
+    if (!g->d_key && (st = dalloc(&g->d_key, (size_t)g->n + 1, acct, "order key"))) return st;
+    int32_t *deg = nullptr, *fa = nullptr, *fb = nullptr;
+    if ((st = dalloc(&deg, (size_t)g->n + 1, nullptr, "peeling")) ||
+        (st = dalloc(&fa, (size_t)g->n + 1, nullptr, "peeling")) ||
+        (st = dalloc(&fb, (size_t)g->n + 1, nullptr, "peeling"))) {
+        dfree(deg); dfree(fa); dfree(fb);
+        return st;
+    }
+    int32_t* cnt = g->d_small->peel;          // [0], [1]: frontier sizes, [2]: smallest degree
+    int32_t* hp = g->h_small->peel;
+    auto sync_read = [&](int32_t* dst, const int32_t* src, int count) -> hipError_t {
+        hipError_t e = hipMemcpyAsync(dst, src, sizeof(int32_t) * (size_t)count, hipMemcpyDeviceToHost, s);
+        return e == hipSuccess ? hipStreamSynchronize(s) : e;
+    };
+    hipError_t e = launch_fill_i32(cnt, 0, 2, s);
+    if (e == hipSuccess) e = launch_fill_i32(cnt + 2, 0x7fffffff, 1, s);
+    if (e == hipSuccess) e = launch_peel_init(g->n, g->d_row_ptr, deg, g->d_key, cnt + 2, s);
+    if (e == hipSuccess) e = sync_read(hp, cnt, 3);
+    int32_t t = hp[2], r = 0, remaining = g->n, nf = 0;
+    int32_t* cur = fa;
+    int32_t* nxt = fb;
+    int cur_slot = 0;
+    while (e == hipSuccess && remaining > 0) {
+        if (nf == 0) {
+            // no vertex left at degree <= t: raise t to the smallest degree present
+            if (r > 0) {
+                e = launch_fill_i32(cnt + 2, 0x7fffffff, 1, s);
+                if (e == hipSuccess) e = launch_peel_min(g->n, deg, g->d_key, cnt + 2, s);
+                if (e == hipSuccess) e = sync_read(hp + 2, cnt + 2, 1);
+                if (e != hipSuccess) break;
+                t = hp[2];
+            }
+            e = launch_fill_i32(cnt + cur_slot, 0, 1, s);
+            if (e == hipSuccess) e = launch_peel_collect(g->n, deg, g->d_key, t, cur, cnt + cur_slot, s);
+            if (e == hipSuccess) e = sync_read(hp + cur_slot, cnt + cur_slot, 1);
+            if (e != hipSuccess) break;
+            nf = hp[cur_slot];
+            if (nf <= 0) { e = hipErrorUnknown; break; }     // cannot happen while vertices remain
+        }
+        e = launch_fill_i32(cnt + (1 - cur_slot), 0, 1, s);
+        if (e == hipSuccess)
+            e = launch_peel_round(nf, cur, g->d_row_ptr, g->d_col, deg, g->d_key, t, r, nxt, cnt + (1 - cur_slot), s);
+        if (e == hipSuccess) e = sync_read(hp + (1 - cur_slot), cnt + (1 - cur_slot), 1);
+        if (e != hipSuccess) break;
+        remaining -= nf;
+        ++r;
+        nf = hp[1 - cur_slot];
+        std::swap(cur, nxt);
+        cur_slot = 1 - cur_slot;
+    }
+    dfree(deg);
+    dfree(fa);
+    dfree(fb);
+    if (e != hipSuccess) return hip_fail(e, "peeling kernels");
+    g->peel_rounds = r;
+    return CITRON_OK;
+}
+
+// Ordering phase: the DAG of the degree ordering (Section IV, Algorithm 3),
+// or of the core ordering (key = peeling round) with the same kernels.
+static citron_status order_impl(citron_graph* g, int kind)
 {
     if (!g) return fail(CITRON_EINVAL, "graph is NULL");
     std::lock_guard<std::mutex> lock(g->mu);
-    if (g->state == 1) return CITRON_OK;
+    if (g->state == 1) {
+        if (g->order_kind == kind) return CITRON_OK;
+        return fail(CITRON_ESTATE, "the graph is already ordered by the other ordering");
+    }
     hipError_t e = hipSetDevice(g->device);
     if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
     int64_t* acct = &g->device_bytes;
@@ -658,12 +790,13 @@ citron_status citron_order(citron_graph* g)
         (!g->d_dag_src && (st = dalloc(&g->d_dag_src, (size_t)g->m, acct, "dag_src"))) ||
         (!g->d_scan_ws && (st = dalloc(&g->d_scan_ws, g->scan_ws_ints, acct, "scan workspace"))))
         return st;
+    if (kind == 1 && g->n > 0 && (st = peel_key(g))) return st;
     hipStream_t s = g->stream;
     int32_t* mx = &g->d_small->max_outdeg;
     e = launch_fill_i32(mx, 0, 1, s);
     if (e == hipSuccess)
         e = launch_orient(g->n, g->d_row_ptr, g->d_col, g->d_outdeg, g->d_dag_ptr, g->d_dag_col,
-                          g->d_dag_src, mx, g->d_scan_ws, s);
+                          g->d_dag_src, mx, g->d_scan_ws, s, kind == 1 ? g->d_key : nullptr);
     if (e == hipSuccess && g->n == 0) e = launch_fill_i32(g->d_dag_ptr, 0, 1, s);
     if (e == hipSuccess)
         e = hipMemcpyAsync(&g->h_small->max_outdeg, mx, sizeof(int32_t), hipMemcpyDeviceToHost, s);
@@ -673,9 +806,40 @@ citron_status citron_order(citron_graph* g)
     if (e != hipSuccess) return hip_fail(e, "ordering kernels");
     if (g->h_small->ends[0] != g->m) return fail(CITRON_EDEVICE, "ordering produced a wrong arc count");
     g->max_outdeg = g->h_small->max_outdeg;
+    g->order_kind = kind;
     g->state = 1;
     // the schedule of the counting phase is part of ordering the graph
     return ensure_plan(g, g->tuning);
+}
+
+citron_status citron_order(citron_graph* g) { return order_impl(g, 0); }
+
+citron_status citron_order_core(citron_graph* g) { return order_impl(g, 1); }
+
+citron_status citron_get_order_key(const citron_graph* g, int32_t* key, int32_t* rounds)
+{
+    if (!g) return fail(CITRON_EINVAL, "graph is NULL");
+    if (g->state != 1) return fail(CITRON_ESTATE, "citron_order or citron_order_core must be called first");
+    if (!key && g->n > 0) return fail(CITRON_EINVAL, "key is NULL");
+    citron_graph* gm = const_cast<citron_graph*>(g);
+    std::lock_guard<std::mutex> lock(gm->mu);
+    if (rounds) *rounds = g->order_kind == 1 ? g->peel_rounds : 0;
+    if (g->n == 0) return CITRON_OK;
+    hipError_t e = hipSetDevice(g->device);
+    if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
+    if (g->order_kind == 1) {
+        e = hipMemcpyAsync(key, g->d_key, sizeof(int32_t) * (size_t)g->n, hipMemcpyDeviceToHost, g->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(g->stream);
+        if (e != hipSuccess) return hip_fail(e, "copying the order key");
+        return CITRON_OK;
+    }
+    // degree ordering: the key is the degree
+    std::vector<int32_t> rp((size_t)g->n + 1);
+    e = hipMemcpyAsync(rp.data(), g->d_row_ptr, sizeof(int32_t) * rp.size(), hipMemcpyDeviceToHost, g->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(g->stream);
+    if (e != hipSuccess) return hip_fail(e, "copying row_ptr");
+    for (int32_t v = 0; v < g->n; ++v) key[v] = rp[(size_t)v + 1] - rp[(size_t)v];
+    return CITRON_OK;
 }
 
 uint64_t citron_count(citron_graph* g, int32_t k, citron_status* st_out)
@@ -689,6 +853,21 @@ uint64_t citron_count(citron_graph* g, int32_t k, citron_status* st_out)
     if (trivial) return v;
     uint64_t c = 0;
     *st = run_single(g, k, nullptr, false, &c);
+    if (*st && *st != CITRON_EOVERFLOW) return 0;
+    return c;
+}
+
+uint64_t citron_count_vertex_rooted(citron_graph* g, int32_t k, citron_status* st_out)
+{
+    citron_status dummy;
+    citron_status* st = st_out ? st_out : &dummy;
+    bool trivial;
+    uint64_t v;
+    *st = check_count_args(g, k, &trivial, &v);
+    if (*st) return 0;
+    if (trivial) return v;
+    uint64_t c = 0;
+    *st = run_single(g, k, nullptr, false, &c, nullptr, 0, 0, 1, nullptr, true);
     if (*st && *st != CITRON_EOVERFLOW) return 0;
     return c;
 }

@@ -21,6 +21,7 @@ struct SmallDev {
     unsigned long long tri_acc;
     int32_t tri_ovf;
     int32_t build_ctr;
+    int32_t peel[4];             // peeling: frontier counts (2), smallest degree, spare
     unsigned long long build_stats[kNumStats];
 };
 
@@ -38,6 +39,7 @@ struct SmallHost {
     uint64_t tri_acc;
     int32_t tri_ovf;
     int32_t rows_total;
+    int32_t peel[4];
     uint64_t build_stats[kNumStats];
 };
 
@@ -50,6 +52,8 @@ struct citron_graph {
     int64_t nnz = 0;
     int64_t m = 0;
     int state = 0;                 // 0 LOADED, 1 ORDERED
+    int order_kind = 0;            // 0 degree ordering, 1 core ordering (peeling)
+    int32_t peel_rounds = 0;       // rounds of the peeling (core ordering)
     int32_t max_outdeg = 0;
     int64_t device_bytes = 0;
     std::mutex mu;
@@ -61,6 +65,7 @@ struct citron_graph {
     int32_t* d_dag_col = nullptr;
     int32_t* d_dag_src = nullptr;
     int32_t* d_scan_ws = nullptr;
+    int32_t* d_key = nullptr;              // core ordering: round of each vertex
     size_t scan_ws_ints = 0;
     citron::SmallDev* d_small = nullptr;
     citron::SmallHost* h_small = nullptr;
@@ -97,6 +102,11 @@ struct citron_graph {
     int64_t bucket_bytes[CITRON_KMAX + 1] = {};   // device bytes of each table
     int32_t n_buckets[CITRON_KMAX + 1] = {};
     int32_t n_work[CITRON_KMAX + 1] = {};
+    // per k: the vertex-rooted schedule (whole vertices, no split)
+    int32_t* d_vbuckets[CITRON_KMAX + 1] = {};
+    int64_t vbucket_bytes[CITRON_KMAX + 1] = {};
+    int32_t n_vbuckets[CITRON_KMAX + 1] = {};
+    int32_t n_vwork[CITRON_KMAX + 1] = {};
     uint64_t build_stats[citron::kNumStats] = {};
 };
 
@@ -111,6 +121,7 @@ int device_cus(int dev);
 citron_status ensure_plan(citron_graph* g, const citron_tuning& t);
 citron_status ensure_rows(citron_graph* g);
 citron_status ensure_buckets(citron_graph* g, int32_t k);
+citron_status ensure_vbuckets(citron_graph* g, int32_t k);
 citron_status check_count_args(const citron_graph* g, int32_t k, bool* trivial, uint64_t* value);
 QueryDesc make_query(const citron_graph* g, int32_t k, unsigned long long* acc, int32_t* ovf,
                      unsigned long long* per_arc, unsigned long long* stats, int32_t item_begin);

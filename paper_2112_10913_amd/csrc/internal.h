@@ -90,9 +90,11 @@ struct QueryDesc {
     // buckets (key |C_uv|) and light-vertex buckets (key out-degree - 1),
     // merged.  Bucket b: buckets[4b] = first item, [4b+1] = first arc (index
     // into harcs) or first light vertex (index into the light part of order),
-    // [4b+2] = arcs or vertices in the bucket, [4b+3] = key << 1 | light.
-    // An arc or vertex is split into parts (arc_parts / light_parts); items
-    // of a bucket are part-major.  buckets[4 n_buckets] = item count.
+    // [4b+2] = arcs or vertices in the bucket, [4b+3] = key << 2 | kind
+    // (BucketKind).  An arc or vertex is split into parts (arc_parts /
+    // light_parts); items of a bucket are part-major.  buckets[4 n_buckets]
+    // = item count.  The vertex-rooted schedule has only the two vertex
+    // kinds, each item one whole vertex (heavy ones indexed in order itself).
     const int32_t* buckets;
     int32_t n_buckets;
     int32_t light_first;         // index in order of the first light vertex
@@ -109,6 +111,14 @@ struct QueryDesc {
     // arc_items[2j+1] >> 16 parts; its counts go to per-arc slot `slot`
     const int32_t* arc_list;
     const int32_t* arc_items;
+};
+
+// Kinds of work item (low two bits of a bucket's key word).
+enum BucketKind {
+    kItemHeavyArc = 0,     // one part of an arc of a heavy vertex (edge-rooted)
+    kItemLightVertex = 1,  // (a part of) a light vertex, its arcs the units (edge-rooted)
+    kItemHeavyVertex = 2,  // a whole heavy vertex, searched from its own root (vertex-rooted)
+    kItemLightRoot = 3     // a whole light vertex, one unit rooted at the vertex (vertex-rooted)
 };
 
 // Parts a heavy arc with |C_uv| = c is split into for a k-clique count; each

@@ -10,9 +10,25 @@ size_t scan_workspace_ints(int64_t n);
 hipError_t scan_exclusive(const int32_t* in, int32_t* out, int64_t n, int32_t* ws, hipStream_t s);
 hipError_t launch_validate(int32_t n, int64_t nnz, const int32_t* row_ptr, const int32_t* col,
                            int32_t* err, int stage, hipStream_t s);
+// key: nullptr for the degree ordering, else the per-vertex order key (ties by id)
 hipError_t launch_orient(int32_t n, const int32_t* row_ptr, const int32_t* col, int32_t* outdeg,
                          int32_t* dag_ptr, int32_t* dag_col, int32_t* dag_src, int32_t* max_outdeg,
-                         int32_t* scan_ws, hipStream_t s);
+                         int32_t* scan_ws, hipStream_t s, const int32_t* key = nullptr);
+
+// ---- core ordering by level-synchronous peeling (kernels_core.hip)
+// deg[v] = degree, round[v] = -1; *min_deg = smallest degree (preset to INT_MAX)
+hipError_t launch_peel_init(int32_t n, const int32_t* row_ptr, int32_t* deg, int32_t* round, int32_t* min_deg,
+                            hipStream_t s);
+// *min_deg = smallest deg over vertices with round < 0 (preset to INT_MAX)
+hipError_t launch_peel_min(int32_t n, const int32_t* deg, const int32_t* round, int32_t* min_deg, hipStream_t s);
+// frontier <- vertices with round < 0 and deg <= t, appended at *cnt
+hipError_t launch_peel_collect(int32_t n, const int32_t* deg, const int32_t* round, int32_t t, int32_t* frontier,
+                               int32_t* cnt, hipStream_t s);
+// round[frontier[i]] = r, then the neighbours still present lose one degree
+// per edge; those that fall to t are appended to next at *next_cnt
+hipError_t launch_peel_round(int32_t nf, const int32_t* frontier, const int32_t* row_ptr, const int32_t* col,
+                             int32_t* deg, int32_t* round, int32_t t, int32_t r, int32_t* next, int32_t* next_cnt,
+                             hipStream_t s);
 
 // ---- vertex schedule (kernels_count.hip)
 struct PlanBuffers {

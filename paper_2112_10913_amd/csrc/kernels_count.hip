@@ -860,6 +860,20 @@ __device__ __forceinline__ void heavy_arc(const HeavyCtx<true>& H, int r, int pa
     }
 }
 
+// Vertex-rooted unit (Algorithm 2 per vertex): the whole subgraph of u, all
+// d positions as candidates and k - 1 vertices still to choose; its first
+// level walks the arcs of u in turn within this one work item.
+template <bool kStats, bool kPerArc, int kRegL>
+__device__ __forceinline__ void heavy_vertex(const HeavyCtx<true>& H, int d, WaveBuf& wb, Acc& A, u64* per_arc)
+{
+    const int q = lane_of();
+    u64 uacc = 0;
+    const int rem = d - 64 * q;
+    const u64 M = q < H.W ? (rem >= 64 ? ~0ull : ((1ull << rem) - 1ull)) : 0ull;
+    if (heavy_node<kStats, kPerArc, true, kRegL>(H, M, d, H.L, 0, 0, 1, wb, A, uacc, per_arc))
+        heavy_dfs<kStats, kPerArc, true, kRegL>(H, M, H.L, 0, 0, 1, wb, A, uacc, per_arc);
+}
+
 // --------------------------------------------------------------- the kernel
 
 struct KParams {
@@ -962,6 +976,7 @@ __global__ void __launch_bounds__(kMaxBlock) count_kernel(KParams P)
         const u64 t_item = kStats ? wall_clock64() : 0ull;
         // the item: one part of a heavy arc, or (a part of) a light vertex
         int u, r = -1, part, nparts, tag;
+        int kind = kItemHeavyArc;
         bool heavy;
         if (q.arc_list) {
             // list mode: one part of one listed arc; counts go to its list slot
@@ -981,21 +996,26 @@ __global__ void __launch_bounds__(kMaxBlock) count_kernel(KParams P)
                 if (q.buckets[4 * mid] <= i) lo = mid;
                 else hi = mid - 1;
             }
-            const int key = q.buckets[4 * lo + 3] >> 1;
-            heavy = (q.buckets[4 * lo + 3] & 1) == 0;
+            const int key = q.buckets[4 * lo + 3] >> 2;
+            kind = q.buckets[4 * lo + 3] & 3;
+            heavy = kind == kItemHeavyArc || kind == kItemHeavyVertex;
             const int cnt = q.buckets[4 * lo + 2];
             const int local = i - q.buckets[4 * lo];
             part = local / cnt;
             const int which = q.buckets[4 * lo + 1] + (local - part * cnt);
-            if (heavy) {
+            if (kind == kItemHeavyArc) {
                 const int e = q.rows.harcs[which];
                 u = q.dag_src[e];
                 r = e - q.dag_ptr[u];
                 nparts = arc_parts(key, k, q.split_pct);
                 tag = e;
+            } else if (kind == kItemHeavyVertex) {
+                u = q.order[which];
+                nparts = 1;
+                tag = -1;
             } else {
                 u = q.order[q.light_first + which];
-                nparts = light_parts(key + 1, k, q.split_pct);
+                nparts = kind == kItemLightVertex ? light_parts(key + 1, k, q.split_pct) : 1;
                 tag = -1;
             }
         }
@@ -1004,7 +1024,23 @@ __global__ void __launch_bounds__(kMaxBlock) count_kernel(KParams P)
         if (heavy) {
             const HeavyCtx<true> H{RowRef<true>{(glb_u64*)(q.rows.rows + q.rows.rows_off[u])},
                                    (d + 63) >> 6, k - 1, tag};
-            heavy_arc<kStats, kPerArc, kRegL>(H, r, part, nparts, wb, A, per_arc);
+            if (kind == kItemHeavyVertex) heavy_vertex<kStats, kPerArc, kRegL>(H, d, wb, A, per_arc);
+            else heavy_arc<kStats, kPerArc, kRegL>(H, r, part, nparts, wb, A, per_arc);
+        } else if (kind == kItemLightRoot) {
+            // vertex-rooted light vertex: its rows, then one unit rooted at
+            // the vertex itself (mask of all d positions, k - 1 to choose)
+            if (wb.n + d + 1 > kWaveBufRows) flush_tasks<kStats, kPerArc, kRegL>(wb, A, per_arc);
+            if (lane < d) {
+                wb.rows[wb.n + lane] = q.rows.rows[q.rows.rows_off[u] + lane];
+                wb.meta[wb.n + lane] = (wb.n << 8) | (k - 2);
+            }
+            if (lane == 0) {
+                wb.rows[wb.n + d] = d >= 64 ? ~0ull : ((1ull << d) - 1ull);
+                wb.meta[wb.n + d] = (wb.n << 8) | (k - 1);
+                wb.units[wb.nu] = wb.n + d;
+            }
+            wb.nu += 1;
+            wb.n += d + 1;
         } else {
             // rows of the vertex into the wave's buffer; the searched arcs
             // (every nparts-th one, or the one listed) become units

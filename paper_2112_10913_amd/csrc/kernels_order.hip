@@ -155,24 +155,33 @@ hipError_t scan_exclusive(const int32_t* in, int32_t* out, int64_t n, int32_t* w
 
 // --------------------------------------------------------------- ordering
 
-// omega(u) < omega(v): lower undirected degree first, ties by lower id.
+// omega(u) < omega(v): lower key first, ties by lower id.  The key is the
+// undirected degree for the degree ordering (Section IV), or the round in
+// which a vertex left the peeling for the core ordering.
 __device__ __forceinline__ bool keeps(int32_t du, int32_t u, int32_t dv, int32_t v)
 {
     return du < dv || (du == dv && u < v);
+}
+
+// key of v: its degree, or key[v] when a key array is given
+__device__ __forceinline__ int32_t key_of(const int32_t* __restrict__ row_ptr, const int32_t* __restrict__ key,
+                                          int32_t v)
+{
+    return key ? key[v] : row_ptr[v + 1] - row_ptr[v];
 }
 
 // Out-degree of every vertex (first loop of Algorithm 3).  One wavefront per
 // vertex; each lane takes four row entries per step so that four neighbour
 // degree gathers are in flight.  Also tracks the largest out-degree.
 __global__ void orient_count_kernel(int32_t n, const int32_t* __restrict__ row_ptr,
-                                    const int32_t* __restrict__ col, int32_t* __restrict__ outdeg,
-                                    int32_t* __restrict__ max_outdeg)
+                                    const int32_t* __restrict__ col, const int32_t* __restrict__ key,
+                                    int32_t* __restrict__ outdeg, int32_t* __restrict__ max_outdeg)
 {
     const int64_t u = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
     if (u >= n) return;
     const int lane = lane_id();
     const int32_t a = row_ptr[u], b = row_ptr[u + 1];
-    const int32_t du = b - a;
+    const int32_t du = key_of(row_ptr, key, (int32_t)u);
     int cnt = 0;
     for (int32_t e0 = a; e0 < b; e0 += 4 * kWave) {
         int32_t v[4], dv[4];
@@ -183,7 +192,7 @@ __global__ void orient_count_kernel(int32_t n, const int32_t* __restrict__ row_p
         }
 #pragma unroll
         for (int j = 0; j < 4; ++j)
-            dv[j] = v[j] >= 0 ? row_ptr[v[j] + 1] - row_ptr[v[j]] : 0;
+            dv[j] = v[j] >= 0 ? key_of(row_ptr, key, v[j]) : 0;
 #pragma unroll
         for (int j = 0; j < 4; ++j)
             cnt += (v[j] >= 0 && keeps(du, (int32_t)u, dv[j], v[j])) ? 1 : 0;
@@ -202,7 +211,7 @@ __global__ void orient_count_kernel(int32_t n, const int32_t* __restrict__ row_p
 // its ascending order.  dag_src (may be null) receives the source vertex of
 // every arc.
 __global__ void orient_scatter_kernel(int32_t n, const int32_t* __restrict__ row_ptr,
-                                      const int32_t* __restrict__ col,
+                                      const int32_t* __restrict__ col, const int32_t* __restrict__ key,
                                       const int32_t* __restrict__ dag_ptr,
                                       int32_t* __restrict__ dag_col, int32_t* __restrict__ dag_src)
 {
@@ -210,7 +219,7 @@ __global__ void orient_scatter_kernel(int32_t n, const int32_t* __restrict__ row
     if (u >= n) return;
     const int lane = lane_id();
     const int32_t a = row_ptr[u], b = row_ptr[u + 1];
-    const int32_t du = b - a;
+    const int32_t du = key_of(row_ptr, key, (int32_t)u);
     int32_t out = dag_ptr[u];
     const unsigned long long below = (lane == 0) ? 0ull : (~0ull >> (kWave - lane));
     for (int32_t e0 = a; e0 < b; e0 += kWave) {
@@ -219,7 +228,7 @@ __global__ void orient_scatter_kernel(int32_t n, const int32_t* __restrict__ row
         bool keep = false;
         if (e < b) {
             v = col[e];
-            keep = keeps(du, (int32_t)u, row_ptr[v + 1] - row_ptr[v], v);
+            keep = keeps(du, (int32_t)u, key_of(row_ptr, key, v), v);
         }
         const unsigned long long mask = __ballot(keep);
         if (keep) {
@@ -248,17 +257,17 @@ hipError_t launch_validate(int32_t n, int64_t nnz, const int32_t* row_ptr, const
 
 hipError_t launch_orient(int32_t n, const int32_t* row_ptr, const int32_t* col, int32_t* outdeg,
                          int32_t* dag_ptr, int32_t* dag_col, int32_t* dag_src, int32_t* max_outdeg,
-                         int32_t* scan_ws, hipStream_t s)
+                         int32_t* scan_ws, hipStream_t s, const int32_t* key)
 {
     if (n == 0) return hipSuccess;
     const int64_t threads = (int64_t)n * kWave;
     const unsigned blocks = (unsigned)((threads + 255) / 256);
-    orient_count_kernel<<<blocks, 256, 0, s>>>(n, row_ptr, col, outdeg, max_outdeg);
+    orient_count_kernel<<<blocks, 256, 0, s>>>(n, row_ptr, col, key, outdeg, max_outdeg);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     e = scan_exclusive(outdeg, dag_ptr, n, scan_ws, s);
     if (e != hipSuccess) return e;
-    orient_scatter_kernel<<<blocks, 256, 0, s>>>(n, row_ptr, col, dag_ptr, dag_col, dag_src);
+    orient_scatter_kernel<<<blocks, 256, 0, s>>>(n, row_ptr, col, key, dag_ptr, dag_col, dag_src);
     return hipGetLastError();
 }
 
