@@ -190,6 +190,28 @@ uint64_t citron_count_part(citron_graph* g, int32_t k, int32_t part, int32_t npa
 uint64_t citron_count_arcs(citron_graph* g, int32_t k, const int32_t* arcs, int32_t n,
                            uint64_t* out, citron_status* st);
 
+/* k-clique listing for selected arcs (the paper's conclusion: listing is a
+ * small change of the counting recursion; Section III-B's edge-rooted unit):
+ * for each arcs[i] = u -> v, every k-clique whose two lowest vertices in
+ * the ordering are u and v, written as k vertex ids in increasing order of
+ * the ordering (u, v, then one vertex per recursion level); the cliques of
+ * an arc follow the depth-first order that takes each level's candidates
+ * by ascending id.  2 <= k <= 16.
+ *   arcs      device int32[n_arcs], arc indices in citron_get_dag order
+ *             (each 0..m-1, else CITRON_EINVAL), 0 <= n_arcs <= 2^26
+ *   offsets   device int64[n_arcs+1], written: the cliques of arc i are
+ *             cliques[offsets[i] .. offsets[i+1]) (exclusive scan of the
+ *             arcs' exact counts); written even when the output is too small
+ *   cliques   device int32[cap * k], written (may be NULL with cap = 0)
+ *   total     host: the number of cliques of all listed arcs
+ * Returns CITRON_ENOMEM, writing no clique, when total > cap (call with
+ * cap = 0 to size the buffer); CITRON_EDEVICE if the listing disagrees
+ * with the count (never expected: both are exact).  Synchronous on the
+ * graph's stream.  The output is 4k bytes per clique: large graphs are
+ * listed by ranges of arcs. */
+citron_status citron_list_arcs(citron_graph* g, int32_t k, const int32_t* arcs, int32_t n_arcs,
+                               int64_t* offsets, int32_t* cliques, int64_t cap, int64_t* total);
+
 /* Many (graph, k) queries in one persistent launch, replayed from a
  * captured HIP graph when the same query set is submitted again.  All
  * graphs must be ORDERED and share one device.  counts and sts are host

@@ -100,6 +100,9 @@ def load_library():
     lib.citron_get_order_key.restype = ctypes.c_int32
     lib.citron_count.argtypes = [vp, ctypes.c_int32, _i32p]
     lib.citron_count.restype = ctypes.c_uint64
+    lib.citron_list_arcs.argtypes = [vp, ctypes.c_int32, vp, ctypes.c_int32, vp, vp, ctypes.c_int64,
+                                     ctypes.POINTER(ctypes.c_int64)]
+    lib.citron_list_arcs.restype = ctypes.c_int32
     lib.citron_count_vertex_rooted.argtypes = [vp, ctypes.c_int32, _i32p]
     lib.citron_count_vertex_rooted.restype = ctypes.c_uint64
     lib.citron_count_per_arc.argtypes = [vp, ctypes.c_int32, vp, _i32p]
@@ -271,6 +274,34 @@ class Graph:
         if ovf:
             raise CitronError(EOVERFLOW, "count is >= 2^64", v)
         return v
+
+    def list_arcs(self, k: int, arcs=None):
+        """k-cliques of the listed arcs (default: every arc): (cliques as an
+        int32 tensor of shape (total, k) on the device, offsets as an int64
+        tensor of n_arcs + 1 entries: the cliques of arc i are rows
+        offsets[i]..offsets[i+1]).  Two calls: the first sizes the output."""
+        torch = _torch()
+        lib = load_library()
+        if arcs is None:
+            arcs = torch.arange(self.m, dtype=torch.int32, device="cuda")
+        elif not (hasattr(arcs, "is_cuda") and arcs.is_cuda):
+            arcs = torch.as_tensor(np.ascontiguousarray(arcs, dtype=np.int32)).cuda()
+        arcs = arcs.to(torch.int32).contiguous()
+        n = arcs.numel()
+        offsets = torch.zeros(n + 1, dtype=torch.int64, device="cuda")
+        total = ctypes.c_int64(0)
+        pa = arcs.data_ptr() if n else None
+        st = lib.citron_list_arcs(self._handle(), int(k), pa, n, offsets.data_ptr(), None, 0,
+                                  ctypes.byref(total))
+        if st not in (OK, ENOMEM):
+            raise _err(st)
+        out = torch.empty((max(total.value, 1), k), dtype=torch.int32, device="cuda")
+        if total.value > 0:
+            st = lib.citron_list_arcs(self._handle(), int(k), pa, n, offsets.data_ptr(), out.data_ptr(),
+                                      total.value, ctypes.byref(total))
+            if st:
+                raise _err(st)
+        return out[:total.value], offsets
 
     def count_vertex_rooted(self, k: int) -> int:
         """The same count with the vertex-rooted unit (one work item per

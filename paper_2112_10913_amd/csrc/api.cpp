@@ -961,6 +961,81 @@ uint64_t citron_count_arcs(citron_graph* g, int32_t k, const int32_t* arcs, int3
     return c;
 }
 
+citron_status citron_list_arcs(citron_graph* g, int32_t k, const int32_t* arcs, int32_t n_arcs, int64_t* offsets,
+                               int32_t* cliques, int64_t cap, int64_t* total)
+{
+    if (!total) return fail(CITRON_EINVAL, "total is NULL");
+    *total = 0;
+    if (!g) return fail(CITRON_EINVAL, "graph is NULL");
+    if (k < 2 || k > kListMaxK) return fail(CITRON_EINVAL, "listing needs 2 <= k <= 16");
+    if (n_arcs < 0 || n_arcs > (1 << 26) || !offsets || (n_arcs > 0 && !arcs))
+        return fail(CITRON_EINVAL, "arc list: NULL pointer or n outside 0..2^26");
+    if (cap < 0) return fail(CITRON_EINVAL, "cap must be >= 0");
+    if (g->state != 1) return fail(CITRON_ESTATE, "citron_order must be called before listing");
+    // exact per-arc counts size the output (checks the arc indices too)
+    unsigned long long* per = nullptr;
+    long long* ws = nullptr;
+    citron_status st = CITRON_OK;
+    hipError_t e = hipSetDevice(g->device);
+    if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
+    const size_t nws = scan64_workspace(n_arcs);
+    if (hipMalloc((void**)&per, sizeof(unsigned long long) * (size_t)std::max(n_arcs, 1)) != hipSuccess ||
+        hipMalloc((void**)&ws, sizeof(long long) * nws) != hipSuccess) {
+        if (per) (void)hipFree(per);
+        return fail(CITRON_ENOMEM, "hipMalloc failed for the listing");
+    }
+    if (n_arcs > 0) {
+        citron_status cst;
+        (void)citron_count_arcs(g, k, arcs, n_arcs, (uint64_t*)per, &cst);
+        if (cst == CITRON_EOVERFLOW) cst = fail(CITRON_EINVAL, "more cliques than a 64-bit count holds");
+        st = cst;
+    }
+    int64_t tot = 0;
+    if (!st) {
+        std::lock_guard<std::mutex> lock(g->mu);
+        hipStream_t s = g->stream;
+        e = scan_exclusive64(per, (long long*)offsets, n_arcs, ws, s);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(&g->h_small->stats[0], offsets + n_arcs, sizeof(int64_t), hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        if (e != hipSuccess) st = hip_fail(e, "listing offsets");
+        tot = (int64_t)g->h_small->stats[0];
+        *total = tot;
+        if (!st && tot > 0 && (tot > cap || !cliques))
+            st = fail(CITRON_ENOMEM, "the output holds fewer cliques than the arcs have (see *total)");
+        if (!st && tot > 0) {
+            if (!g->rows_valid) st = ensure_rows(g);
+            ListParams P;
+            P.arcs = arcs;
+            P.n_arcs = n_arcs;
+            P.k = k;
+            P.dag_ptr = g->d_dag_ptr;
+            P.dag_col = g->d_dag_col;
+            P.dag_src = g->d_dag_src;
+            P.rows_off = g->d_rows_off;
+            P.rows = g->d_rows;
+            P.offsets = (const long long*)offsets;
+            P.out = cliques;
+            P.cursor = &g->d_small->item_ctr;
+            P.err = &g->d_small->err;
+            if (!st) {
+                e = launch_fill_i32(P.cursor, 0, 1, s);
+                if (e == hipSuccess) e = launch_fill_i32(P.err, 0, 1, s);
+                if (e == hipSuccess) e = launch_list_arcs(P, device_cus(g->device) * 8, s);
+                if (e == hipSuccess)
+                    e = hipMemcpyAsync(&g->h_small->err, P.err, sizeof(int32_t), hipMemcpyDeviceToHost, s);
+                if (e == hipSuccess) e = hipStreamSynchronize(s);
+                if (e != hipSuccess) st = hip_fail(e, "listing kernel");
+                else if (g->h_small->err)
+                    st = fail(CITRON_EDEVICE, "listing found a different number of cliques than the count");
+            }
+        }
+    }
+    (void)hipFree(per);
+    (void)hipFree(ws);
+    return st;
+}
+
 citron_status citron_work_stats(citron_graph* g, int32_t k, uint64_t* stats)
 {
     if (!stats) return fail(CITRON_EINVAL, "stats is NULL");

@@ -98,4 +98,25 @@ hipError_t launch_list_items(int32_t n, const int32_t* parts, const int32_t* off
 hipError_t launch_gather_arc_c(const int32_t* arcs, int32_t n, const int32_t* arc_c, unsigned long long* out,
                                hipStream_t s);
 
+// ---- k-clique listing (kernels_list.hip)
+constexpr int kListMaxK = 16;                    // largest k listing supports
+constexpr int kListMaxLevels = kListMaxK - 2;    // open search levels per wave
+struct ListParams {
+    const int32_t* arcs;         // listed arcs (DAG arc indices)
+    int32_t n_arcs;
+    int32_t k;
+    const int32_t* dag_ptr;
+    const int32_t* dag_col;
+    const int32_t* dag_src;
+    const int32_t* rows_off;
+    const unsigned long long* rows;
+    const long long* offsets;    // n_arcs + 1: first output clique of each arc
+    int32_t* out;                // cliques, k ids each
+    int32_t* cursor;             // zeroed before the launch
+    int32_t* err;                // zeroed before the launch; 1 = slot overrun, 2 = count mismatch
+};
+hipError_t launch_list_arcs(const ListParams& P, int32_t blocks, hipStream_t s);
+size_t scan64_workspace(int64_t n);
+hipError_t scan_exclusive64(const unsigned long long* in, long long* out, int64_t n, long long* ws, hipStream_t s);
+
 }  // namespace citron
