@@ -235,7 +235,10 @@ citron_status citron_graph_info(const citron_graph* g, int64_t* n, int64_t* m,
 /* Per-graph tuning (copied).  NULL restores the defaults.  Zero fields
  * take their defaults (wg_waves 4, blocks_per_cu 2, light_rows 256,
  * flush_rows 128, build_blocks_per_cu 4, split_pct 100, arc_lds_max 256).
- * Not to be changed while the graph is registered with a server. */
+ * A change of split_pct gives later counts a new schedule; work already
+ * admitted by a server or captured in a batch keeps the schedule it was
+ * built with (superseded schedules stay allocated until citron_free), so a
+ * change at any time is safe and never alters a count. */
 citron_status citron_set_tuning(citron_graph* g, const citron_tuning* t);
 citron_status citron_get_tuning(const citron_graph* g, citron_tuning* t);
 

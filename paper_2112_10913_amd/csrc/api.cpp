@@ -137,6 +137,8 @@ static void free_graph_memory(citron_graph* g)
     dfree(g->d_hhist);
     dfree(g->d_hscan);
     dfree(g->d_hcur);
+    for (int32_t* p : g->retired_buckets) dfree(p);
+    g->retired_buckets.clear();
     for (int k = 0; k <= CITRON_KMAX; ++k) {
         dfree(g->d_buckets[k]);
         g->bucket_bytes[k] = 0;
@@ -303,9 +305,12 @@ citron_status ensure_buckets(citron_graph* g, int32_t k)
 {
     const int32_t pct = g->tuning.split_pct;
     if (g->d_buckets[k] && g->bucket_split[k] == pct) return CITRON_OK;
-    dfree(g->d_buckets[k]);
-    g->device_bytes -= g->bucket_bytes[k];
-    g->bucket_bytes[k] = 0;
+    if (g->d_buckets[k]) {
+        // another split: the old table stays valid for readers that hold it
+        // (a captured batch, an admitted request) until the graph is freed
+        g->retired_buckets.push_back(g->d_buckets[k]);
+        g->d_buckets[k] = nullptr;
+    }
     const int32_t D = std::max(g->max_outdeg, 2);
     auto v_at_least = [&](int32_t x) -> int64_t {   // vertices with out-degree >= x
         if (x > D) return 0;
@@ -348,7 +353,7 @@ citron_status ensure_buckets(citron_graph* g, int32_t k)
     tab.push_back(0);
     citron_status st = dalloc(&g->d_buckets[k], tab.size(), &g->device_bytes, "item buckets");
     if (st) return st;
-    g->bucket_bytes[k] = (int64_t)(sizeof(int32_t) * tab.size());
+    g->bucket_bytes[k] += (int64_t)(sizeof(int32_t) * tab.size());   // retired tables stay counted
     hipError_t e = hipMemcpy(g->d_buckets[k], tab.data(), sizeof(int32_t) * tab.size(), hipMemcpyHostToDevice);
     if (e != hipSuccess) return hip_fail(e, "item buckets");
     g->n_buckets[k] = nb;

@@ -98,6 +98,9 @@ struct citron_graph {
     bool tri_ovf = false;
     // per k: the merged bucket table of the count's work items
     int32_t* d_buckets[CITRON_KMAX + 1] = {};
+    // tables superseded by a split change: kept until the graph is freed,
+    // since a captured batch or an admitted server request may still read one
+    std::vector<int32_t*> retired_buckets;
     int32_t bucket_split[CITRON_KMAX + 1] = {};   // split_pct each table was built with
     int64_t bucket_bytes[CITRON_KMAX + 1] = {};   // device bytes of each table
     int32_t n_buckets[CITRON_KMAX + 1] = {};
