@@ -77,7 +77,8 @@ typedef struct {
                                 (batches of vertices with out-degree <= 64):
                                 64..1024, a multiple of 64 */
     int32_t flush_rows;      /* one-word subgraph rows a wave queues before it
-                                searches them: 64..256 */
+                                searches them: 64..256 (at most the queue's
+                                128 rows take effect) */
     int32_t build_blocks_per_cu; /* persistent build workgroups per compute
                                 unit: 1..16 */
     int32_t split_pct;       /* scale of the number of parts a heavy arc or a
@@ -233,8 +234,8 @@ citron_status citron_graph_info(const citron_graph* g, int64_t* n, int64_t* m,
                                 int32_t* max_outdeg, int64_t* device_bytes);
 
 /* Per-graph tuning (copied).  NULL restores the defaults.  Zero fields
- * take their defaults (wg_waves 4, blocks_per_cu 2, light_rows 256,
- * flush_rows 128, build_blocks_per_cu 4, split_pct 100, arc_lds_max 256).
+ * take their defaults (wg_waves 4, blocks_per_cu 4, light_rows 256,
+ * flush_rows 128, build_blocks_per_cu 4, split_pct 100, arc_lds_max 192).
  * A change of split_pct gives later counts a new schedule; work already
  * admitted by a server or captured in a batch keeps the schedule it was
  * built with (superseded schedules stay allocated until citron_free), so a

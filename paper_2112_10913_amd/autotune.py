@@ -30,11 +30,12 @@ from ._lib import CitronError, Tuning, count_batch, device_info
 DEFAULT_SPACE = {
     "wg_waves": [1, 2, 4, 8],
     "blocks_per_cu": [1, 2, 4, 8],
-    "flush_rows": [64, 128, 192],
+    "flush_rows": [64, 128],
     "arc_lds_max": [128, 192, 256],
     "split_pct": [50, 100, 200],
 }
-# waves per CU worth trying: LDS holds at most 8 count waves (k <= 8)
+# waves per CU worth trying: registers allow 16 count waves (k <= 8: 128
+# VGPRs, 4 per SIMD), LDS 16 with LDS copies up to 192 candidates
 MAX_WAVES_PER_CU = 16
 
 

@@ -32,12 +32,12 @@ citron_tuning default_tuning()
     citron_tuning t;
     t.size = sizeof(citron_tuning);
     t.wg_waves = 4;
-    t.blocks_per_cu = 2;
+    t.blocks_per_cu = 4;        // 16 waves per CU (the count kernel is latency-bound)
     t.light_rows = 256;
     t.flush_rows = 128;
     t.build_blocks_per_cu = 4;
     t.split_pct = 100;
-    t.arc_lds_max = 256;
+    t.arc_lds_max = 192;        // LDS copies of 192 candidates keep 16 waves within 160 KB
     return t;
 }
 
@@ -593,7 +593,7 @@ static citron_status run_single(citron_graph* g, int32_t k, unsigned long long* 
     cl.max_k = stack_k;
     cl.blocks = blocks;
     cl.wg_waves = wg;
-    cl.lds_bytes = count_lds_bytes(0, stack_k, wg);
+    cl.lds_bytes = count_lds_bytes(t.arc_lds_max, stack_k, wg, per_arc != nullptr);
     cl.flush_rows = t.flush_rows;
     cl.arc_lds_max = t.arc_lds_max;
     cl.stats = stats;

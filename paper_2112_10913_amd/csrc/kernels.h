@@ -88,8 +88,12 @@ struct CountLaunch {
     bool stats;                 // instrumented launch
     bool per_arc;               // some query writes per-arc counts
 };
+// device-memory stack words per block of a count launch
 int64_t count_scratch_words(int32_t max_deg, int32_t max_k, int32_t wg_waves);
-int32_t count_lds_bytes(int32_t light_rows, int32_t max_k, int32_t wg_waves);
+// the part of them that grows with k (all stacks of k > 12)
+int64_t count_deep_scratch_words(int32_t max_k, int32_t wg_waves);
+// dynamic LDS of a count launch: arc_max is its arc_lds_max tuning value
+int32_t count_lds_bytes(int32_t arc_max, int32_t max_k, int32_t wg_waves, bool per_arc);
 hipError_t launch_count(const CountLaunch& cl, hipStream_t s);
 hipError_t launch_check_arcs(const int32_t* arcs, int32_t n, int64_t m, int32_t* err, hipStream_t s);
 hipError_t launch_list_parts(const int32_t* arcs, int32_t n, const int32_t* dag_src, const int32_t* dag_ptr,

@@ -36,16 +36,17 @@ namespace citron {
 typedef unsigned long long u64;
 
 constexpr int kMaxBlock = 512;          // threads per count workgroup (8 waves)
-constexpr int kWaveBufRows = 256;       // one-word rows queued per wave
+constexpr int kWaveBufRows = 128;       // one-word rows queued per wave
 constexpr int kLdsStackLevels = 8;      // deeper stacks (k > 12) live in device memory
 constexpr int kArcMaxC = kArcLdsMax;    // LDS subgraph copies hold at most this many rows
-constexpr int kArcWords = kArcMaxC * (kArcMaxC / 64);   // 8 KB per wave
 constexpr int kLaneMaxWords = 4;        // multi-word masks a lane holds in registers
 constexpr int kDonateMinIdle = 8;       // idle lanes that trigger work donation
 constexpr int kBurstIters = 32;         // last-level steps of one leaf burst at most
 constexpr int kBurstMinLanes = 32;      // lanes at a last-level node to keep a burst going
 constexpr int kN3Burst = 8;             // two-level steps between refills of idle lanes
-constexpr int kPosList = 512;           // candidate positions the mailbox area holds (2 KB)
+// donation mailbox per lane: M, R, (need, base), and the arc tag of per-arc launches
+__host__ __device__ constexpr int mbox_words(bool per_arc) { return per_arc ? 4 : 3; }
+constexpr int kPosList = 3 * kWave * 2; // candidate positions the smaller mailbox area holds (1.5 KB)
 static_assert(kArcMaxC <= kPosList, "candidate positions of an LDS node fit the mailbox area");
 
 // ------------------------------------------------------------------ helpers
@@ -157,8 +158,10 @@ __device__ __forceinline__ int wave_select(u64 m, int j, int W)
 __host__ __device__ inline int stack_levels(int max_k) { return max_k > 4 ? max_k - 4 : 1; }
 
 // Where the search stacks live, by the largest k of a launch: light stacks
-// in registers and heavy stacks in LDS (k <= 8), all in LDS (k <= 12), or
-// all in device memory.
+// in registers and heavy stacks in device memory (k <= 8: the heavy stacks
+// are touched only when a heavy node is pushed or popped, and keeping them
+// out of LDS lets more waves share a CU), all in LDS (k <= 12), or all in
+// device memory.
 constexpr int kRegLevels = 4;
 enum StackMode { kStackReg = 0, kStackLds = 1, kStackGlobal = 2 };
 __host__ __device__ inline int stack_mode(int max_k)
@@ -168,27 +171,57 @@ __host__ __device__ inline int stack_mode(int max_k)
 }
 // per wave: four stacks (light M/R, heavy M/R) of levels x 64 words
 __host__ __device__ inline int64_t wave_stack_words(int max_k) { return 4ll * stack_levels(max_k) * kWave; }
-__host__ __device__ inline int wave_lds_bytes(int max_k)
+// the part of them kept in device memory, per wave
+__host__ __device__ inline int64_t wave_global_stack_words(int max_k)
 {
-    int b = 8 * kWaveBufRows + 4 * kWaveBufRows + 4 * kWaveBufRows;   // rows, meta, tags
-    b += 8 * kArcWords;                                               // arc subgraph copy
-    b += 32 * kWave;                                                  // donation mailbox
-    b += 4 * kWaveBufRows;                                            // unit list
     const int mode = stack_mode(max_k);
-    if (mode == kStackReg) b += 8 * (int)wave_stack_words(max_k) / 2;   // heavy stacks only
-    if (mode == kStackLds) b += 8 * (int)wave_stack_words(max_k);
-    return b;
+    return mode == kStackGlobal ? wave_stack_words(max_k) : (mode == kStackReg ? wave_stack_words(max_k) / 2 : 0);
 }
 
-int32_t count_lds_bytes(int32_t, int32_t max_k, int32_t wg_waves)
+// Largest LDS subgraph copy of a launch: nodes with 64 < c <= arc_max
+// candidates, ceil(arc_max / 64) words per row.
+__host__ __device__ inline int clamp_arc_max(int arc_max)
 {
-    return wg_waves * wave_lds_bytes(max_k);
+    return arc_max < kWave ? kWave : (arc_max > kArcMaxC ? kArcMaxC : arc_max);
+}
+__host__ __device__ inline int arc_copy_words(int arc_max)
+{
+    const int a = clamp_arc_max(arc_max);
+    return a * ((a + 63) / 64);
+}
+
+// Per-wave LDS, in this order: queued rows (u64), their meta (i32), their
+// arc tags (i32, per-arc launches only), the subgraph copy (u64), the
+// donation mailbox (u64 per lane), the unit list (i32), the stacks kept in
+// LDS.  Every part starts 8-byte aligned; the size is rounded to 16 bytes.
+// The LDS per wave bounds the waves per CU (160 KB per CU), and the count
+// kernel is latency-bound, so the layout is sized by what a launch uses.
+__host__ __device__ inline int wave_lds_bytes(int max_k, int arc_max, bool per_arc)
+{
+    int b = 8 * kWaveBufRows + 4 * kWaveBufRows + (per_arc ? 4 * kWaveBufRows : 0);
+    b += 8 * arc_copy_words(arc_max);
+    b += 8 * mbox_words(per_arc) * kWave;
+    b += 4 * kWaveBufRows;
+    if (stack_mode(max_k) == kStackLds) b += 8 * (int)wave_stack_words(max_k);
+    return (b + 15) & ~15;
+}
+
+int32_t count_lds_bytes(int32_t arc_max, int32_t max_k, int32_t wg_waves, bool per_arc)
+{
+    return wg_waves * wave_lds_bytes(max_k, arc_max, per_arc);
+}
+
+int64_t count_deep_scratch_words(int32_t max_k, int32_t wg_waves)
+{
+    if (stack_mode(max_k) != kStackGlobal) return 0;
+    return ((int64_t)wg_waves * wave_stack_words(max_k) + 31) & ~31ll;
 }
 
 int64_t count_scratch_words(int32_t, int32_t max_k, int32_t wg_waves)
 {
-    if (stack_mode(max_k) != kStackGlobal) return 0;
-    return ((int64_t)wg_waves * wave_stack_words(max_k) + 31) & ~31ll;
+    const int64_t w = wave_global_stack_words(max_k);
+    if (w == 0) return 0;
+    return ((int64_t)wg_waves * w + 31) & ~31ll;
 }
 
 // ------------------------------------------------------------ light engine
@@ -359,22 +392,22 @@ __device__ __forceinline__ void light_engine(const WaveBuf& wb, Acc& A, u64* __r
                         const u64 low = Rl & ((1ull << p) - 1);
                         if (lvl == t) R = low;
                         else stk.set_r(lvl - 1, low);
-                        u64* mb = wb.mbox + 4 * recv;
+                        u64* mb = wb.mbox + mbox_words(kPerArc) * recv;
                         mb[0] = Ml;
                         mb[1] = Rl & ~low;
                         mb[2] = ((u64)(unsigned)base << 32) | (unsigned)(need + (t - lvl));
-                        mb[3] = (u64)(unsigned)tag;
+                        if (kPerArc) mb[3] = (u64)(unsigned)tag;
                     }
                 }
                 __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
                 __builtin_amdgcn_wave_barrier();
                 if (!active && __popcll(idle & lt_mask) < np) {
-                    const u64* mb = wb.mbox + 4 * lane;
+                    const u64* mb = wb.mbox + mbox_words(kPerArc) * lane;
                     M = mb[0];
                     R = mb[1];
                     need = (int)(unsigned)mb[2];
                     base = (int)(mb[2] >> 32);
-                    tag = (int)(unsigned)mb[3];
+                    if (kPerArc) tag = (int)(unsigned)mb[3];
                     t = 1;
                     uacc = 0;
                     active = true;
@@ -889,7 +922,7 @@ struct KParams {
 };
 
 template <int kMode, bool kStats, bool kPerArc>
-__global__ void __launch_bounds__(kMaxBlock) count_kernel(KParams P)
+__global__ void __launch_bounds__(kMaxBlock) __attribute__((amdgpu_waves_per_eu(kMode == kStackReg ? 4 : 2))) count_kernel(KParams P)
 {
     constexpr int kRegL = kMode == kStackReg ? kRegLevels : 0;
     extern __shared__ __align__(16) unsigned char smem[];
@@ -897,19 +930,26 @@ __global__ void __launch_bounds__(kMaxBlock) count_kernel(KParams P)
     const int wid = threadIdx.x / kWave;
     const int nwaves = blockDim.x / kWave;
     const int levels = stack_levels(P.max_k);
-    unsigned char* wbase = smem + wid * wave_lds_bytes(P.max_k);
+    unsigned char* wbase = smem + wid * wave_lds_bytes(P.max_k, P.arc_lds_max, kPerArc);
     WaveBuf wb;
-    wb.rows = reinterpret_cast<u64*>(wbase);
-    wb.meta = reinterpret_cast<int32_t*>(wbase + 8 * kWaveBufRows);
-    wb.tags = reinterpret_cast<int32_t*>(wbase + 12 * kWaveBufRows);
-    wb.arc = reinterpret_cast<u64*>(wbase + 16 * kWaveBufRows);
-    wb.mbox = reinterpret_cast<u64*>(wbase + 16 * kWaveBufRows + 8 * kArcWords);
-    wb.units = reinterpret_cast<int32_t*>(wbase + 16 * kWaveBufRows + 8 * kArcWords + 32 * kWave);
+    int off = 0;
+    wb.rows = reinterpret_cast<u64*>(wbase + off);
+    off += 8 * kWaveBufRows;
+    wb.meta = reinterpret_cast<int32_t*>(wbase + off);
+    off += 4 * kWaveBufRows;
+    wb.tags = reinterpret_cast<int32_t*>(wbase + off);     // per-arc launches only
+    if (kPerArc) off += 4 * kWaveBufRows;
+    wb.arc = reinterpret_cast<u64*>(wbase + off);
+    off += 8 * arc_copy_words(P.arc_lds_max);
+    wb.mbox = reinterpret_cast<u64*>(wbase + off);
+    off += 8 * mbox_words(kPerArc) * kWave;
+    wb.units = reinterpret_cast<int32_t*>(wbase + off);
+    off += 4 * kWaveBufRows;
     u64* stacks;
-    if (kMode == kStackGlobal)
-        stacks = P.scratch + (int64_t)blockIdx.x * P.scratch_words + (int64_t)wid * wave_stack_words(P.max_k);
+    if (kMode == kStackLds)
+        stacks = reinterpret_cast<u64*>(wbase + off);
     else
-        stacks = reinterpret_cast<u64*>(wbase + 20 * kWaveBufRows + 8 * kArcWords + 32 * kWave);
+        stacks = P.scratch + (int64_t)blockIdx.x * P.scratch_words + (int64_t)wid * wave_global_stack_words(P.max_k);
     (void)nwaves;
     if (kMode == kStackReg) {
         wb.sM = nullptr;
@@ -1119,8 +1159,9 @@ hipError_t launch_count(const CountLaunch& cl, hipStream_t s)
     P.scratch = cl.scratch;
     P.scratch_words = cl.scratch_words;
     P.max_k = cl.max_k;
-    P.flush_rows = cl.flush_rows;
-    P.arc_lds_max = cl.arc_lds_max < kWave ? kWave : (cl.arc_lds_max > kArcMaxC ? kArcMaxC : cl.arc_lds_max);
+    // a wave runs its queue once it holds flush_rows rows (at most its buffer)
+    P.flush_rows = cl.flush_rows > kWaveBufRows ? kWaveBufRows : cl.flush_rows;
+    P.arc_lds_max = clamp_arc_max(cl.arc_lds_max);
     switch (stack_mode(cl.max_k)) {
     case kStackReg: return launch_mode<kStackReg>(P, cl, s);
     case kStackLds: return launch_mode<kStackLds>(P, cl, s);

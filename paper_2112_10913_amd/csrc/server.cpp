@@ -118,7 +118,7 @@ int64_t footprint_of(const citron_server* s, int32_t k)
 {
     int64_t b = (int64_t)sizeof(QueryDesc) + 16;
     const int64_t blocks = (int64_t)device_cus(s->device) * s->tuning.blocks_per_cu;
-    b += count_scratch_words(0, k, s->tuning.wg_waves) * 8 * blocks;
+    b += count_deep_scratch_words(k, s->tuning.wg_waves) * 8 * blocks;
     return b;
 }
 
@@ -181,7 +181,7 @@ bool issue_step(citron_server* s, Step& st, bool fast, int wg, int32_t blocks)
         cl.max_k = maxk;
         cl.blocks = blocks;
         cl.wg_waves = wg;
-        cl.lds_bytes = count_lds_bytes(0, maxk, wg);
+        cl.lds_bytes = count_lds_bytes(s->tuning.arc_lds_max, maxk, wg, false);
         cl.flush_rows = s->tuning.flush_rows;
         cl.arc_lds_max = s->tuning.arc_lds_max;
         cl.stats = false;
