@@ -88,7 +88,10 @@ typedef struct {
     int32_t arc_lds_max;     /* subgraph representation switch: nodes with at
                                 most this many candidates (and more than 64)
                                 are copied to LDS, larger ones are walked in
-                                device memory: 64..256 */
+                                device memory: 64..256, or 0 (the default)
+                                to let the library choose by k (256 for
+                                k <= 5, 224 for k = 6, 192 above: the copy's
+                                LDS bounds the waves per CU) */
 } citron_tuning;
 
 /* ------------------------------------------------------------- graphs */
@@ -234,8 +237,9 @@ citron_status citron_graph_info(const citron_graph* g, int64_t* n, int64_t* m,
                                 int32_t* max_outdeg, int64_t* device_bytes);
 
 /* Per-graph tuning (copied).  NULL restores the defaults.  Zero fields
- * take their defaults (wg_waves 4, blocks_per_cu 4, light_rows 256,
- * flush_rows 128, build_blocks_per_cu 4, split_pct 100, arc_lds_max 192).
+ * take their defaults (wg_waves 2, blocks_per_cu 8, light_rows 256,
+ * flush_rows 128, build_blocks_per_cu 4, split_pct 100, arc_lds_max chosen
+ * by k).
  * A change of split_pct gives later counts a new schedule; work already
  * admitted by a server or captured in a batch keeps the schedule it was
  * built with (superseded schedules stay allocated until citron_free), so a

@@ -31,14 +31,25 @@ citron_tuning default_tuning()
 {
     citron_tuning t;
     t.size = sizeof(citron_tuning);
-    t.wg_waves = 4;
-    t.blocks_per_cu = 4;        // 16 waves per CU (the count kernel is latency-bound)
+    t.wg_waves = 2;
+    t.blocks_per_cu = 8;        // 16 waves per CU (the count kernel is latency-bound)
     t.light_rows = 256;
     t.flush_rows = 128;
     t.build_blocks_per_cu = 4;
     t.split_pct = 100;
-    t.arc_lds_max = 192;        // LDS copies of 192 candidates keep 16 waves within 160 KB
+    t.arc_lds_max = 0;          // by k (arc_max_for)
     return t;
+}
+
+// Largest node copied to LDS for a launch whose largest k is max_k, when
+// the tuning leaves it to the library: at k <= 5 the copies of up to 256
+// candidates pay for the fewer waves their LDS allows (12 per CU); deeper
+// counts gain more from 16 waves per CU, which LDS holds with copies of up
+// to 192 candidates (224 at k = 6: 14 waves).  Measured on R-MAT 20.
+int32_t arc_max_for(const citron_tuning& t, int32_t max_k)
+{
+    if (t.arc_lds_max) return t.arc_lds_max;
+    return max_k <= 5 ? 256 : (max_k == 6 ? 224 : 192);
 }
 
 citron_status resolve_tuning(const citron_tuning* in, citron_tuning* out)
@@ -63,8 +74,8 @@ citron_status resolve_tuning(const citron_tuning* in, citron_tuning* out)
     if (t.build_blocks_per_cu < 1 || t.build_blocks_per_cu > 16)
         return fail(CITRON_EINVAL, "build_blocks_per_cu must be in 1..16");
     if (t.split_pct < 25 || t.split_pct > 400) return fail(CITRON_EINVAL, "split_pct must be in 25..400");
-    if (t.arc_lds_max < 64 || t.arc_lds_max > kArcLdsMax)
-        return fail(CITRON_EINVAL, "arc_lds_max must be in 64..256");
+    if (t.arc_lds_max != 0 && (t.arc_lds_max < 64 || t.arc_lds_max > kArcLdsMax))
+        return fail(CITRON_EINVAL, "arc_lds_max must be 0 (by k) or in 64..256");
     *out = t;
     return CITRON_OK;
 }
@@ -593,9 +604,9 @@ static citron_status run_single(citron_graph* g, int32_t k, unsigned long long* 
     cl.max_k = stack_k;
     cl.blocks = blocks;
     cl.wg_waves = wg;
-    cl.lds_bytes = count_lds_bytes(t.arc_lds_max, stack_k, wg, per_arc != nullptr);
+    cl.lds_bytes = count_lds_bytes(arc_max_for(t, stack_k), stack_k, wg, per_arc != nullptr);
     cl.flush_rows = t.flush_rows;
-    cl.arc_lds_max = t.arc_lds_max;
+    cl.arc_lds_max = arc_max_for(t, stack_k);
     cl.stats = stats;
     cl.per_arc = per_arc != nullptr;
     e = launch_count(cl, s);

@@ -120,6 +120,7 @@ citron_status fail(citron_status st, const std::string& msg);
 citron_status hip_fail(hipError_t e, const char* what);
 citron_tuning default_tuning();
 citron_status resolve_tuning(const citron_tuning* in, citron_tuning* out);
+int32_t arc_max_for(const citron_tuning& t, int32_t max_k);
 int device_cus(int dev);
 citron_status ensure_plan(citron_graph* g, const citron_tuning& t);
 citron_status ensure_rows(citron_graph* g);

@@ -130,9 +130,9 @@ citron_status batch_build(const BatchKey& key, const citron_tuning& t, BatchExec
     cl.max_k = max_k;
     cl.blocks = blocks;
     cl.wg_waves = wg;
-    cl.lds_bytes = count_lds_bytes(t.arc_lds_max, max_k, wg, false);
+    cl.lds_bytes = count_lds_bytes(arc_max_for(t, max_k), max_k, wg, false);
     cl.flush_rows = t.flush_rows;
-    cl.arc_lds_max = t.arc_lds_max;
+    cl.arc_lds_max = arc_max_for(t, max_k);
     cl.stats = false;
     cl.per_arc = false;
 

@@ -181,9 +181,9 @@ bool issue_step(citron_server* s, Step& st, bool fast, int wg, int32_t blocks)
         cl.max_k = maxk;
         cl.blocks = blocks;
         cl.wg_waves = wg;
-        cl.lds_bytes = count_lds_bytes(s->tuning.arc_lds_max, maxk, wg, false);
+        cl.lds_bytes = count_lds_bytes(arc_max_for(s->tuning, maxk), maxk, wg, false);
         cl.flush_rows = s->tuning.flush_rows;
-        cl.arc_lds_max = s->tuning.arc_lds_max;
+        cl.arc_lds_max = arc_max_for(s->tuning, maxk);
         cl.stats = false;
         cl.per_arc = false;
         e = launch_count(cl, st.stream);
