@@ -165,11 +165,55 @@ def alg_bytes(gold, k):
     return float(4 * st["kept_sum_duv"] + 4 * st["kept_sum_dw"] + 8 * (st["kept_sum_s"] + st["arcs_kept"]))
 
 
+def batch_with_progress(citron, gs, ks, every_s=20.0):
+    """count_batch(gs, ks) on a worker thread; this thread reports the
+    launch's progress (work items claimed, read from the device) while it
+    runs.  Returns (counts, seconds)."""
+    import threading
+    out = {}
+
+    def work():
+        t = time.perf_counter()
+        try:
+            out["counts"] = citron.count_batch(gs, ks)
+        except Exception as e:          # re-raised below
+            out["error"] = e
+        out["s"] = time.perf_counter() - t
+
+    th = threading.Thread(target=work)
+    th.start()
+    last = -1
+    while th.is_alive():
+        th.join(timeout=every_s)
+        if th.is_alive():
+            taken, total = citron.batch_progress()
+            if total and taken != last:
+                log(f"    batch launch: {taken} of {total} work items claimed")
+                last = taken
+    if "error" in out:
+        raise out["error"]
+    return out["counts"], out["s"]
+
+
+def batch_class(name, n, k):
+    """Query class of the batched suite: family, size band and k."""
+    if name.startswith("rmat"):
+        sc = int(name[4:].split("_")[0])
+        band = "small" if sc <= 12 else ("mid" if sc <= 14 else "large")
+        return f"rmat-{band}-k{k}"
+    band = "small" if n <= 10000 else ("mid" if n <= 30000 else "large")
+    return f"er-{band}-k{k}"
+
+
 def run_batch(args, citron, gg, torch, graphs):
     """Batched form: a mixed suite of graphs, every graph queried at every k
-    of args.ks, in one persistent launch (replayed from its captured HIP
-    graph) against the same queries as sequential plain counts."""
-    from paper_2112_10913_amd.autotune import autotune
+    of --batch-ks, in one persistent launch (captured into a HIP graph on the
+    first call, replayed later) against the same queries as sequential plain
+    counts; the ratio overall and per query class (family, size band, k),
+    each class's queries also run as a batch of their own.  Counts are
+    checked against the plain counts and against the oracle's stored counts
+    of the suite's pinned members (tests/golden/batch512.json)."""
+    t_start = time.perf_counter()
     hs = []
     for i, x in enumerate(graphs):
         h = citron.Graph.from_csr(x.row_ptr, x.col).order()
@@ -178,43 +222,124 @@ def run_batch(args, citron, gg, torch, graphs):
         if i % 64 == 63:
             log(f"  loaded {i + 1} graphs")
     torch.cuda.synchronize()
-    gs = [h for h in hs for _ in args.ks]
-    ks = [k for _ in hs for k in args.ks]
+    bks = args.batch_ks
+    qs = [(i, k) for i in range(len(hs)) for k in bks]
+    gs = [hs[i] for i, _ in qs]
+    ks = [k for _, k in qs]
+    cls = [batch_class(graphs[i].name, graphs[i].n, k) for i, k in qs]
     log(f"{len(ks)} queries; sequential plain counts")
+    plain, t_q = [], []
     t = time.perf_counter()
-    plain = []
-    for i, (h, k) in enumerate(zip(gs, ks)):
+    for j, (h, k) in enumerate(zip(gs, ks)):
+        t1 = time.perf_counter()
         plain.append(h.count(k))
-        if i % 256 == 255:
-            log(f"  {i + 1} plain counts, {time.perf_counter() - t:.1f} s")
+        t_q.append(time.perf_counter() - t1)
+        if j % 256 == 255:
+            log(f"  {j + 1} plain counts, {time.perf_counter() - t:.1f} s")
     t_seq = time.perf_counter() - t
-    log(f"  sequential {t_seq:.2f} s; autotuning the batched launch")
-    trials = [citron.Tuning(wg_waves=w, blocks_per_cu=b, flush_rows=128) for w, b in ((4, 2), (2, 4), (8, 1))]
-    best, report = autotune(gs, ks, tunings=trials, reps=1, use_cache=False, log=log)
-    got = citron.count_batch(gs, ks, tuning=best)          # captured
-    reps = []
-    for r in range(args.steps):
-        t = time.perf_counter()
-        got = citron.count_batch(gs, ks, tuning=best)
-        reps.append(time.perf_counter() - t)
-        log(f"  batched replay {r + 1}: {reps[-1]:.3f} s")
+    log(f"  sequential {t_seq:.2f} s; batched launch")
+    got, t_first = batch_with_progress(citron, gs, ks)    # captured, then run
+    log(f"  batched (capture + run) {t_first:.2f} s")
     if got != plain:
         raise SystemExit("batched counts differ from plain counts")
-    t_b = float(np.median(reps))
+    t_replay = None
+    if time.perf_counter() - t_start + t_first < args.budget_s:
+        got, t_replay = batch_with_progress(citron, gs, ks)
+        log(f"  batched replay {t_replay:.2f} s")
+        if got != plain:
+            raise SystemExit("batched replay differs from plain counts")
+    # the oracle's stored counts of the pinned members
+    gold = load_golden("batch512")
+    pinned = 0
+    if gold and len(graphs) == gold["suite"]["count"]:
+        pos = {m["position"]: m for m in gold["members"]}
+        for (i, k), c in zip(qs, got):
+            if i in pos and str(k) in pos[i]["counts"]:
+                if c != pos[i]["counts"][str(k)]["count"]:
+                    raise SystemExit(f"batched count differs from the oracle: {graphs[i].name} k={k}")
+                pinned += 1
+    # per class: the class's sequential time and its own batched launch
+    by = {}
+    for j, c in enumerate(cls):
+        by.setdefault(c, []).append(j)
+    per_class = []
+    for c in sorted(by, key=lambda c: sum(t_q[j] for j in by[c])):
+        js = by[c]
+        seq = sum(t_q[j] for j in js)
+        rec = {"class": c, "queries": len(js), "sequential_s": seq}
+        if time.perf_counter() - t_start + 2 * seq < args.budget_s:
+            sub_g, sub_k = [gs[j] for j in js], [ks[j] for j in js]
+            batch_with_progress(citron, sub_g, sub_k)       # capture
+            sub, rec["batched_s"] = batch_with_progress(citron, sub_g, sub_k)
+            rec["speedup"] = seq / rec["batched_s"]
+            if sub != [plain[j] for j in js]:
+                raise SystemExit(f"class {c}: batched counts differ from plain counts")
+        per_class.append(rec)
+        log(f"  {rec}")
+    t_b = t_replay if t_replay is not None else t_first
     line = {
         "metric": "k-clique count time & edges/s per (graph,k); batched/served vs plain; p99 lat",
         "form": "batched", "value": len(ks) / t_b, "unit": "queries/s", "n_gpus": 1,
-        "steps": args.steps, "warmup": 1, "ms_per_step": t_b * 1e3, "higher_is_better": True,
+        "steps": 1, "warmup": 0, "ms_per_step": t_b * 1e3, "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "u64", "data": "synthetic",
         "config": {"workload": f"batch of {len(graphs)} graphs (R-MAT scale 8..16, edge factor 8..32; "
                                f"Erdos-Renyi n 1k..50k, mean degree 10..40; seeds 4000+i), "
-                               f"k = {args.ks}", "queries": len(ks),
+                               f"k = {bks}", "queries": len(ks),
                    "edges_total": int(sum(x.m for x in graphs))},
-        "sequential_plain_s": t_seq, "batched_s": t_b, "speedup_vs_sequential": t_seq / t_b,
-        "counts_equal": True, "tuning": best.__dict__,
-        "autotune_trials": [(tr["tuning"]["wg_waves"], tr["tuning"]["blocks_per_cu"], tr["seconds"])
-                            for tr in report["trials"]],
+        "sequential_plain_s": t_seq, "batched_first_call_s": t_first, "batched_replay_s": t_replay,
+        "speedup_vs_sequential": t_seq / t_b, "counts_equal_plain": True,
+        "counts_equal_oracle_pinned": pinned, "per_class": per_class,
     }
+    print(json.dumps(line), flush=True)
+
+
+def run_list(args, citron, gg, torch):
+    """Listing form: every k-clique of the workload graph, listed arc by arc
+    (citron_list_arcs over all arcs: per-arc counts, their scan, the
+    listing launch), for each k of --ks; output-bound, 4k bytes per clique.
+    The number listed is checked against the oracle's stored count."""
+    g = gg.config_graph(args.workload)
+    gold = load_golden(args.workload)
+    h = citron.Graph.from_csr(g.row_ptr, g.col).order()
+    h.count(3)
+    arcs = torch.arange(g.m, dtype=torch.int32, device="cuda")
+    per_k = {}
+    for k in args.ks:
+        got, offs = h.list_arcs(k, arcs)                  # sizes the buffers (allocator warm)
+        n_cl = int(got.shape[0])
+        del got, offs
+        torch.cuda.synchronize()
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record()
+        got, offs = h.list_arcs(k, arcs)
+        b.record()
+        b.synchronize()
+        ms = a.elapsed_time(b)
+        rec = {"cliques": n_cl, "ms": ms, "cliques_per_s": n_cl / (ms / 1e3),
+               "output_GBps": 4 * k * n_cl / (ms / 1e3) / 1e9}
+        if gold and str(k) in gold.get("counts", {}):
+            rec["equals_oracle_count"] = n_cl == gold["counts"][str(k)]["count"]
+        per_k[str(k)] = rec
+        log(f"  k={k}: {rec}")
+        del got, offs
+        torch.cuda.empty_cache()
+    tot_cl = sum(r["cliques"] for r in per_k.values())
+    tot_s = sum(r["ms"] for r in per_k.values()) / 1e3
+    line = {
+        "metric": "k-clique count time & edges/s per (graph,k); batched/served vs plain; p99 lat",
+        "form": "listing", "value": tot_cl / tot_s, "unit": "cliques/s", "n_gpus": 1, "steps": 1,
+        "warmup": 1, "ms_per_step": tot_s * 1e3, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "i32", "data": "synthetic",
+        "config": {"workload": f"{args.workload}: " + WORKLOADS.get(args.workload, args.workload),
+                   "n": g.n, "m": g.m, "ks": args.ks, "arcs": "all"},
+        "per_k": per_k,
+        "roofline": {"bound": "hbm", "unit": "GB/s", "peak": PEAK_HBM_GBS,
+                     "achieved": sum(4 * int(k) * r["cliques"] for k, r in per_k.items()) / tot_s / 1e9,
+                     "note": "bytes of clique output written over the listing time (per-arc counts, scan "
+                             "and listing launch)"},
+    }
+    line["roofline"]["frac"] = line["roofline"]["achieved"] / PEAK_HBM_GBS
     print(json.dumps(line), flush=True)
 
 
@@ -357,10 +482,12 @@ def main():
                     help="also run instrumented launches and report the kernel's work counters")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a 1 GiB device-to-device copy (reference for HBM counters)")
-    ap.add_argument("--form", choices=["plain", "batch", "serve"], default="plain",
+    ap.add_argument("--form", choices=["plain", "batch", "serve", "list"], default="plain",
                     help="plain (default): the workload above; batch / serve: the batched and "
                          "served forms against sequential plain counts")
     ap.add_argument("--batch-graphs", type=int, default=512)
+    ap.add_argument("--batch-ks", type=int, nargs="+", default=[3, 4, 5, 6, 7, 8],
+                    help="the k values every graph of the batched suite is queried at")
     ap.add_argument("--serve-graphs", type=int, default=64)
     ap.add_argument("--serve-requests", type=int, default=600)
     ap.add_argument("--serve-scale-max", type=int, default=16)
@@ -394,7 +521,7 @@ def main():
         log(f"generated {len(pre)} graphs, m = {sum(x.m for x in pre)} in "
             f"{time.perf_counter() - t:.1f} s")
 
-    if args.form in ("batch", "serve"):
+    if args.form in ("batch", "serve", "list"):
         import torch
         import paper_2112_10913_amd as citron
 
@@ -405,6 +532,8 @@ def main():
         torch.cuda.synchronize()
         if args.form == "batch":
             return run_batch(args, citron, gg, torch, pre)
+        if args.form == "list":
+            return run_list(args, citron, gg, torch)
         return run_serve(args, citron, gg, torch)
     t = time.perf_counter()
     g = gg.config_graph(args.workload)
@@ -582,6 +711,7 @@ def main():
         "vs_baseline": None, "dtype": "u64", "data": "synthetic",
         "config": {"workload": f"{args.workload}: " + WORKLOADS.get(args.workload, args.workload),
                    "n": g.n, "m": m, "ks": args.ks, "max_outdeg": info["max_outdeg"],
+                   "device_bytes": info["device_bytes"],
                    "ordering": args.order, "unit": args.unit, "parallelism": "single GPU"},
         "t_order_ms_mean": float(np.mean(order_ms)),
         "per_k": per_k,

@@ -226,6 +226,14 @@ citron_status citron_count_batch(citron_graph* const* gs, const int32_t* ks, int
                                  uint64_t* counts, citron_status* sts,
                                  const citron_tuning* t);
 
+/* Progress of the citron_count_batch launch running now (for a thread
+ * other than the one that called citron_count_batch): *items_taken = work
+ * items claimed so far by the launch's waves (in steps of 512),
+ * *items_total = its items; both 0 when no batch launch is running.  The
+ * kernel stores its progress into a host-mapped word, so this call makes
+ * no HIP call and never waits for the device. */
+citron_status citron_batch_progress(int32_t* items_taken, int32_t* items_total);
+
 /* Copy the DAG to host memory: dag_ptr int32[n+1], dag_col int32[m], in
  * the arc order of Algorithm 3 (rows by source id, each row ascending), for
  * whichever ordering the graph was ordered by. */

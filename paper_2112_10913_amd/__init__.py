@@ -14,9 +14,9 @@ raise.
 """
 from __future__ import annotations
 
-from ._lib import (CitronError, Graph, Server, Tuning, count_batch, device_info,
+from ._lib import (CitronError, Graph, Server, Tuning, batch_progress, count_batch, device_info,
                    lib_path, load_library, order_noalloc, STATUS_NAMES, NSTATS, STAT_NAMES, KMAX)
 
-__all__ = ["CitronError", "Graph", "Server", "Tuning", "count_batch", "device_info",
+__all__ = ["CitronError", "Graph", "Server", "Tuning", "batch_progress", "count_batch", "device_info",
            "lib_path", "load_library", "order_noalloc", "STATUS_NAMES", "NSTATS", "STAT_NAMES",
            "KMAX"]

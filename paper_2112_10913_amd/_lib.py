@@ -100,6 +100,8 @@ def load_library():
     lib.citron_get_order_key.restype = ctypes.c_int32
     lib.citron_count.argtypes = [vp, ctypes.c_int32, _i32p]
     lib.citron_count.restype = ctypes.c_uint64
+    lib.citron_batch_progress.argtypes = [_i32p, _i32p]
+    lib.citron_batch_progress.restype = ctypes.c_int32
     lib.citron_list_arcs.argtypes = [vp, ctypes.c_int32, vp, ctypes.c_int32, vp, vp, ctypes.c_int64,
                                      ctypes.POINTER(ctypes.c_int64)]
     lib.citron_list_arcs.restype = ctypes.c_int32
@@ -430,6 +432,17 @@ def order_noalloc(row_ptr, col, dag_ptr, dag_col, stream=None) -> int:
     if st:
         raise _err(st)
     return mx.value
+
+
+def batch_progress() -> tuple[int, int]:
+    """(items claimed, items total) of the batch launch running now, from
+    another thread; (0, 0) when none runs."""
+    a = ctypes.c_int32(0)
+    b = ctypes.c_int32(0)
+    st = load_library().citron_batch_progress(ctypes.byref(a), ctypes.byref(b))
+    if st:
+        raise _err(st)
+    return a.value, b.value
 
 
 def count_batch(graphs, ks, tuning: Tuning | None = None, return_status: bool = False):

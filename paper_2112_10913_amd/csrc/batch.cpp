@@ -33,6 +33,7 @@ struct BatchKey {
 struct BatchExec {
     int device = 0;
     int32_t nq = 0;                    // kernel queries
+    int32_t total_items = 0;           // work items of the launch
     std::vector<int32_t> qmap;         // kernel query -> caller index
     unsigned long long* d_acc = nullptr;  // nq
     int32_t* d_ovf = nullptr;          // nq
@@ -63,6 +64,32 @@ struct BatchExec {
 
 std::mutex g_batch_mu;
 std::map<BatchKey, std::unique_ptr<BatchExec>> g_cache;
+
+// Progress of the batch launch in flight, for queries from other threads:
+// the kernel stores the items claimed (every 512th) into a host-mapped
+// pinned word, which the host reads without any HIP call (a copy from the
+// device could wait for compute units the launch holds).  Its device
+// address is baked into captured launches, so the word lives until the
+// process ends.  g_progress_mu guards the published total.
+std::mutex g_progress_mu;
+int32_t g_run_total = 0;
+volatile int32_t* g_progress_word = nullptr;
+int32_t* g_progress_dev = nullptr;
+
+// The host-mapped progress word (allocated once, by the first batch).
+int32_t* progress_device_word()
+{
+    if (!g_progress_dev) {
+        void* h = nullptr;
+        void* d = nullptr;
+        if (hipHostMalloc(&h, 64, hipHostMallocMapped | hipHostMallocCoherent) != hipSuccess) return nullptr;
+        if (hipHostGetDevicePointer(&d, h, 0) != hipSuccess) { (void)hipHostFree(h); return nullptr; }
+        *static_cast<volatile int32_t*>(h) = 0;
+        g_progress_word = static_cast<volatile int32_t*>(h);
+        g_progress_dev = static_cast<int32_t*>(d);
+    }
+    return g_progress_dev;
+}
 hipStream_t g_stream[64] = {nullptr};
 constexpr size_t kMaxCached = 16;
 
@@ -119,6 +146,7 @@ citron_status batch_build(const BatchKey& key, const citron_tuning& t, BatchExec
         total_items += be->h_q[i].n_items;
     }
     be->nq = nq;
+    be->total_items = total_items;
 
     CountLaunch cl;
     cl.queries = be->d_q;
@@ -135,6 +163,7 @@ citron_status batch_build(const BatchKey& key, const citron_tuning& t, BatchExec
     cl.arc_lds_max = arc_max_for(t, max_k);
     cl.stats = false;
     cl.per_arc = false;
+    cl.progress = progress_device_word();   // null: no progress reports
 
     // capture: resets, descriptor upload, kernel, download
     e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
@@ -243,8 +272,17 @@ extern "C" citron_status citron_count_batch(citron_graph* const* gs, const int32
                 it = g_cache.emplace(kkey, std::move(be)).first;
             }
             BatchExec* be = it->second.get();
+            {
+                std::lock_guard<std::mutex> pl(g_progress_mu);
+                if (g_progress_word) *g_progress_word = 0;
+                g_run_total = be->total_items;
+            }
             e = hipGraphLaunch(be->exec, s);
             if (e == hipSuccess) e = hipStreamSynchronize(s);
+            {
+                std::lock_guard<std::mutex> pl(g_progress_mu);
+                g_run_total = 0;
+            }
             if (e != hipSuccess) return hip_fail(e, "batch launch");
             for (int32_t j = 0; j < be->nq; ++j) {
                 const int32_t i = kmap[j];
@@ -260,4 +298,14 @@ extern "C" citron_status citron_count_batch(citron_graph* const* gs, const int32
     }
     if (first == CITRON_EOVERFLOW) fail(CITRON_EOVERFLOW, "a batch count is >= 2^64");
     return first;
+}
+
+extern "C" citron_status citron_batch_progress(int32_t* items_taken, int32_t* items_total)
+{
+    if (!items_taken || !items_total) return fail(CITRON_EINVAL, "NULL argument");
+    std::lock_guard<std::mutex> pl(g_progress_mu);
+    *items_total = g_run_total;
+    const int32_t v = (g_run_total && g_progress_word) ? *g_progress_word : 0;
+    *items_taken = v < g_run_total ? v : g_run_total;
+    return CITRON_OK;
 }

@@ -87,6 +87,7 @@ struct CountLaunch {
     int32_t arc_lds_max = 256;  // heavy nodes with 64 < c <= this are copied to LDS
     bool stats;                 // instrumented launch
     bool per_arc;               // some query writes per-arc counts
+    int32_t* progress = nullptr;   // host-mapped word for the items claimed (nullable)
 };
 // device-memory stack words per block of a count launch
 int64_t count_scratch_words(int32_t max_deg, int32_t max_k, int32_t wg_waves);

@@ -919,6 +919,7 @@ struct KParams {
     int32_t max_k;
     int32_t flush_rows;     // a wave runs its queue once it holds this many rows
     int32_t arc_lds_max;    // representation switch of heavy nodes (64..kArcMaxC)
+    int32_t* progress;      // host-mapped word: items claimed, updated every 512 (nullable)
 };
 
 template <int kMode, bool kStats, bool kPerArc>
@@ -986,6 +987,9 @@ __global__ void __launch_bounds__(kMaxBlock) __attribute__((amdgpu_waves_per_eu(
         if (lane == 0) g = atomicAdd(P.item_ctr, 1);
         g = __shfl(g, 0, kWave);
         if (g >= P.total_items) break;
+        // progress for the host, read without any HIP call while the launch runs
+        if (P.progress && lane == 0 && (g & 511) == 0)
+            __hip_atomic_store(P.progress, g, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
         int qi = 0;
         {
             int lo = 0, hi = P.n_queries - 1;
@@ -1162,6 +1166,7 @@ hipError_t launch_count(const CountLaunch& cl, hipStream_t s)
     // a wave runs its queue once it holds flush_rows rows (at most its buffer)
     P.flush_rows = cl.flush_rows > kWaveBufRows ? kWaveBufRows : cl.flush_rows;
     P.arc_lds_max = clamp_arc_max(cl.arc_lds_max);
+    P.progress = cl.progress;
     switch (stack_mode(cl.max_k)) {
     case kStackReg: return launch_mode<kStackReg>(P, cl, s);
     case kStackLds: return launch_mode<kStackLds>(P, cl, s);

@@ -98,3 +98,26 @@ def test_mixed_suite_of_512_graphs_against_the_oracle(citron_gpu, progress):
         if j % 500 == 499:
             progress(f"  {j + 1} plain counts, {time.perf_counter() - t:.1f} s")
     assert got == plain
+
+
+def test_progress_of_a_running_batch(citron_gpu):
+    """citron_batch_progress from another thread while a batch runs: the
+    items claimed grow, never exceed the total, and read (0, 0) after."""
+    import threading
+    g = gg.rmat(15, 28, seed=4456)
+    h = citron_gpu.Graph.from_csr(g.row_ptr, g.col).order()
+    want = h.count(7)
+    out = {}
+    th = threading.Thread(target=lambda: out.setdefault("c", citron_gpu.count_batch([h, h], [7, 6])))
+    th.start()
+    seen = []
+    while th.is_alive():
+        taken, total = citron_gpu.batch_progress()
+        if total:
+            assert 0 <= taken <= total
+            seen.append(taken)
+        time.sleep(0.005)
+    th.join()
+    assert out["c"][0] == want
+    assert seen and seen[-1] >= seen[0]
+    assert citron_gpu.batch_progress() == (0, 0)
