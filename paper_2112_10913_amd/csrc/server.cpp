@@ -9,10 +9,14 @@
 // the next step and share the device with them.  Two lanes keep small
 // requests from waiting behind large ones:
 //   - fast lane (one stream): requests with at most kFastItems items, whole;
-//   - heavy lane (two streams): one larger request per step, in admission
-//     order, up to kHeavyStepItems of its items, so that a step works on one
-//     graph (its rows stay in cache); two such steps run at once, and while
-//     one drains its last items the other takes the freed compute units.
+//   - heavy lane (two streams): one larger request per step, the requests
+//     taken in turn, a slice of its items sized to run about kHeavyStepTargetMs
+//     (each request's slice is rescaled from the measured time of its last
+//     step), so that a step works on one graph (its rows stay in cache) and
+//     a step's persistent grid frees the compute units again within tens
+//     of milliseconds for requests that arrive meanwhile; two such steps run
+//     at once, and while one drains its last items the other takes the
+//     freed compute units.
 // Steps of a lane retire in issue order; a request whose items have all
 // retired returns its count and frees its slot.  Counts are exact integers,
 // so a request's count does not depend on which requests it shares steps
@@ -48,6 +52,7 @@ struct Req {
     int32_t slot = -1;
     int32_t n_items = 0;
     int32_t issued = 0;       // items handed to steps
+    int32_t slice = 0;        // heavy lane: items of its next step
     int32_t retired = 0;      // items of retired steps
     bool failed = false;      // a step with its items failed: issue no more
     int64_t footprint = 0;
@@ -56,15 +61,21 @@ struct Req {
 
 // Lanes: a request with at most kFastItems items goes whole into one fast
 // step (at most kFastStepItems items); larger ones are sliced into heavy
-// steps of at most kHeavyStepItems items, each step one request's slice.
+// steps, each step one request's slice: kHeavyFirstSlice items first, then
+// rescaled toward kHeavyStepTargetMs per step within [kHeavyMinSlice,
+// kHeavyMaxSlice] (its items come largest first, so later slices grow).
 constexpr int32_t kFastItems = 4096;
 constexpr int32_t kFastStepItems = 65536;
-constexpr int32_t kHeavyStepItems = 1 << 20;
+constexpr int32_t kHeavyFirstSlice = 4096;
+constexpr int32_t kHeavyMinSlice = 1024;
+constexpr int32_t kHeavyMaxSlice = 1 << 22;
+constexpr float kHeavyStepTargetMs = 25.0f;
 constexpr int kInflight = 3;              // step 0: fast lane; 1, 2: heavy lane
 
 // One step's launch resources (reused once the step has retired).
 struct Step {
     hipStream_t stream = nullptr;
+    hipEvent_t start = nullptr;          // timing of heavy steps
     hipEvent_t done = nullptr;
     QueryDesc* d_q = nullptr;            // max_slots descriptors
     QueryDesc* h_q = nullptr;            // pinned staging of the same
@@ -106,6 +117,7 @@ struct citron_server {
     unsigned long long* h_acc = nullptr;
     int32_t* h_ovf = nullptr;
     int64_t next_id = 0;
+    int64_t rr_last = -1;                 // heavy lane: request of the last heavy step
     std::string worker_error;
 };
 
@@ -147,15 +159,34 @@ bool issue_step(citron_server* s, Step& st, bool fast, int wg, int32_t blocks)
     for (const Req& r : s->active)
         if (r.fast == fast && !r.failed && r.issued < r.n_items) ++with_work;
     if (with_work == 0) return false;
-    const int32_t cap = fast ? kFastStepItems : kHeavyStepItems;
+    const int32_t cap = fast ? kFastStepItems : kHeavyMaxSlice;
     int32_t total = 0, maxk = 4, nq = 0;
     st.parts.clear();
-    for (Req& r : s->active) {   // admission order
+    // fast lane: admission order; heavy lane: round robin over the heavy
+    // requests with items left, from the one after the last served, so that
+    // a request needing a few steps is not held behind a long one
+    const size_t na = s->active.size();
+    size_t first = 0;
+    if (!fast && na > 0) {
+        size_t best = na;
+        for (size_t j = 0; j < na; ++j) {
+            const Req& r = s->active[j];
+            if (r.fast || r.failed || r.issued >= r.n_items) continue;
+            if (best == na) best = j;                         // wrap-around choice
+            if (r.id > s->rr_last) { best = j; break; }       // next after the last served
+        }
+        first = best == na ? 0 : best;
+    }
+    for (size_t jj = first; jj < na; ++jj) {
+        Req& r = s->active[jj];
         if (r.fast != fast || r.failed || r.issued >= r.n_items) continue;
         if (total >= cap) break;
         int32_t take = r.n_items - r.issued;
         if (fast && total + take > cap && total > 0) break;
-        if (!fast) take = std::min(take, cap);
+        if (!fast) {
+            if (r.slice <= 0) r.slice = kHeavyFirstSlice;
+            take = std::min(take, r.slice);
+        }
         QueryDesc q = r.q;
         q.item_begin = total;
         q.item_lo = r.issued;
@@ -165,9 +196,13 @@ bool issue_step(citron_server* s, Step& st, bool fast, int wg, int32_t blocks)
         r.issued += take;
         total += take;
         maxk = std::max(maxk, r.k);
-        if (!fast) break;            // one request per heavy step
+        if (!fast) {                 // one request per heavy step
+            s->rr_last = r.id;
+            break;
+        }
     }
-    hipError_t e = launch_fill_i32(st.d_item_ctr, 0, 1, st.stream);
+    hipError_t e = hipEventRecord(st.start, st.stream);
+    if (e == hipSuccess) e = launch_fill_i32(st.d_item_ctr, 0, 1, st.stream);
     if (e == hipSuccess)
         e = hipMemcpyAsync(st.d_q, st.h_q, sizeof(QueryDesc) * (size_t)nq, hipMemcpyHostToDevice, st.stream);
     if (e == hipSuccess) {
@@ -196,15 +231,23 @@ bool issue_step(citron_server* s, Step& st, bool fast, int wg, int32_t blocks)
 // Retire a step: credit its items to their requests.  A failed step marks
 // its requests failed; they finish once every step holding their items has
 // retired, so that no step still adds into a slot that is handed on.
-void retire_step(citron_server* s, Step& st)
+void retire_step(citron_server* s, Step& st, bool fast)
 {
     hipError_t e = st.err;
     if (e == hipSuccess) e = hipEventSynchronize(st.done);
+    float ms = 0.0f;
+    if (e == hipSuccess && !fast && hipEventElapsedTime(&ms, st.start, st.done) != hipSuccess) ms = 0.0f;
     for (const auto& pr : st.parts)
         for (Req& r : s->active)
             if (r.id == pr.first) {
                 r.retired += pr.second;
                 if (e != hipSuccess) r.failed = true;
+                if (!fast && ms > 0.0f && pr.second >= r.slice) {
+                    // next slice of this request toward the step target
+                    const double scaled = (double)r.slice * kHeavyStepTargetMs / ms;
+                    r.slice = (int32_t)std::min<double>(kHeavyMaxSlice,
+                                                        std::max<double>(kHeavyMinSlice, scaled));
+                }
             }
     if (e != hipSuccess) s->worker_error = hipGetErrorString(e);
     st.parts.clear();
@@ -304,14 +347,14 @@ void worker_main(citron_server* s)
         bool retired = false;
         for (;;) {
             if (fast_busy && (s->steps[0].err != hipSuccess || hipEventQuery(s->steps[0].done) != hipErrorNotReady)) {
-                retire_step(s, s->steps[0]);
+                retire_step(s, s->steps[0], true);
                 fast_busy = false;
                 retired = true;
             }
             while (!heavy_inflight.empty()) {
                 Step& st = s->steps[heavy_inflight.front()];
                 if (st.err == hipSuccess && hipEventQuery(st.done) == hipErrorNotReady) break;
-                retire_step(s, st);
+                retire_step(s, st, false);
                 heavy_free.push_back(heavy_inflight.front());
                 heavy_inflight.pop_front();
                 retired = true;
@@ -369,6 +412,7 @@ void server_free(citron_server* s)
         if (st.d_item_ctr) (void)hipFree(st.d_item_ctr);
         if (st.d_scratch) (void)hipFree(st.d_scratch);
         if (st.done) (void)hipEventDestroy(st.done);
+        if (st.start) (void)hipEventDestroy(st.start);
         if (st.stream) (void)hipStreamDestroy(st.stream);
     }
     if (s->d_acc) (void)hipFree(s->d_acc);
@@ -404,7 +448,8 @@ citron_server* citron_server_create(int64_t hbm_budget_bytes, int32_t max_slots,
     if (e == hipSuccess) e = hipHostMalloc((void**)&s->h_ovf, sizeof(int32_t) * (size_t)max_slots, hipHostMallocDefault);
     for (Step& st : s->steps) {
         if (e == hipSuccess) e = hipStreamCreateWithFlags(&st.stream, hipStreamNonBlocking);
-        if (e == hipSuccess) e = hipEventCreateWithFlags(&st.done, hipEventDisableTiming);
+        if (e == hipSuccess) e = hipEventCreate(&st.start);
+        if (e == hipSuccess) e = hipEventCreate(&st.done);
         if (e == hipSuccess) e = hipMalloc((void**)&st.d_q, sizeof(QueryDesc) * (size_t)max_slots);
         if (e == hipSuccess)
             e = hipHostMalloc((void**)&st.h_q, sizeof(QueryDesc) * (size_t)max_slots, hipHostMallocDefault);
