@@ -174,8 +174,11 @@ uint64_t citron_count_per_arc(citron_graph* g, int32_t k, uint64_t* per_arc,
  * part, part + nparts, part + 2 nparts, ... of the count's cost-ordered
  * schedule (each item is one part of a heavy arc or of a light vertex; the
  * k-cliques are the sum over arcs of Section III-B's edge-rooted counts, so
- * the shares add up to the count, mod 2^64).  For progress reporting and
- * for splitting a long count over several calls.  0 <= part < nparts,
+ * the shares add up to the count, mod 2^64).  The schedule breaks every
+ * tie by vertex or arc id, so it depends on the graph and the tuning only:
+ * shares taken by different handles of one graph, in one process or in
+ * several, also add up to the count.  For progress reporting and for
+ * splitting a long count over several calls.  0 <= part < nparts,
  * else CITRON_EINVAL; k <= 3 and trivial k give the whole value in part 0
  * and 0 elsewhere.  Synchronous on the graph's stream. */
 uint64_t citron_count_part(citron_graph* g, int32_t k, int32_t part, int32_t nparts, citron_status* st);

@@ -9,7 +9,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libcitron.so")
 SOURCES = ["kernels_order.hip", "kernels_rows.hip", "kernels_count.hip", "api.cpp", "batch.cpp", "server.cpp",
-           "noalloc.hip", "kernels_core.hip", "kernels_list.hip"]
+           "noalloc.hip", "kernels_core.hip", "kernels_list.hip", "kernels_sched.hip"]
 ARCH = os.environ.get("CITRON_ARCH", "gfx950")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 

@@ -147,7 +147,6 @@ static void free_graph_memory(citron_graph* g)
     dfree(g->d_harcs);
     dfree(g->d_hhist);
     dfree(g->d_hscan);
-    dfree(g->d_hcur);
     for (int32_t* p : g->retired_buckets) dfree(p);
     g->retired_buckets.clear();
     for (int k = 0; k <= CITRON_KMAX; ++k) {
@@ -184,7 +183,30 @@ citron_status ensure_plan(citron_graph* g, const citron_tuning& t)
             (!g->pb.header && (st = dalloc(&g->pb.header, 1, acct, "plan"))))
             return st;
     }
-    e = launch_plan(g->n, g->d_dag_ptr, g->max_outdeg, t.light_rows, 0, 1, g->pb, g->d_scan_ws, g->stream);
+    SortBuffers sb = {};
+    {
+        citron_status st;
+        const size_t tb = sched_sort_temp_bytes(g->n);
+        if (tb == 0) return fail(CITRON_EDEVICE, "sort workspace query failed");
+        unsigned char* tmp = nullptr;
+        if ((st = dalloc(&sb.keys_a, (size_t)g->n + 1, nullptr, "plan order")) ||
+            (st = dalloc(&sb.keys_b, (size_t)g->n + 1, nullptr, "plan order")) ||
+            (st = dalloc(&tmp, tb, nullptr, "plan order"))) {
+            dfree(sb.keys_a);
+            dfree(sb.keys_b);
+            return st;
+        }
+        sb.temp = tmp;
+        sb.temp_bytes = tb;
+    }
+    e = launch_plan(g->n, g->d_dag_ptr, g->max_outdeg, t.light_rows, 0, 1, g->pb, g->d_scan_ws, sb, g->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(g->stream);
+    dfree(sb.keys_a);
+    dfree(sb.keys_b);
+    {
+        unsigned char* tmp = static_cast<unsigned char*>(sb.temp);
+        dfree(tmp);
+    }
     if (e != hipSuccess) return hip_fail(e, "plan kernels");
     g->h_vscan.assign((size_t)D, 0);
     e = hipMemcpyAsync(&g->h_small->plan, g->pb.header, sizeof(PlanHeader), hipMemcpyDeviceToHost, g->stream);
@@ -217,8 +239,7 @@ citron_status ensure_rows(citron_graph* g)
         (!g->d_arc_c && (st = dalloc(&g->d_arc_c, (size_t)g->m, acct, "arc sizes"))) ||
         (!g->d_harcs && (st = dalloc(&g->d_harcs, (size_t)g->m, acct, "heavy arcs"))) ||
         (!g->d_hhist && (st = dalloc(&g->d_hhist, (size_t)D + 1, acct, "arc histogram"))) ||
-        (!g->d_hscan && (st = dalloc(&g->d_hscan, (size_t)D + 1, acct, "arc histogram"))) ||
-        (!g->d_hcur && (st = dalloc(&g->d_hcur, (size_t)D + 1, acct, "arc histogram"))))
+        (!g->d_hscan && (st = dalloc(&g->d_hscan, (size_t)D + 1, acct, "arc histogram"))))
         return st;
     // Row offsets are int32, so the rows of all vertices, sum over u of
     // d(u) * ceil(d(u)/64) words, must stay below 2^31.  That sum is at most
@@ -274,8 +295,30 @@ citron_status ensure_rows(citron_graph* g)
     P.build_stats = sd->build_stats;
     e = launch_build_rows(P, device_cus(g->device) * g->tuning.build_blocks_per_cu, s);
     if (e != hipSuccess) return hip_fail(e, "subgraph build");
+    SortBuffers sb = {};
+    {
+        const size_t tb = sched_sort_temp_bytes(g->m);
+        if (tb == 0) return fail(CITRON_EDEVICE, "sort workspace query failed");
+        unsigned char* tmp = nullptr;
+        if ((st = dalloc(&sb.keys_a, (size_t)g->m + 1, nullptr, "arc schedule")) ||
+            (st = dalloc(&sb.keys_b, (size_t)g->m + 1, nullptr, "arc schedule")) ||
+            (st = dalloc(&tmp, tb, nullptr, "arc schedule"))) {
+            dfree(sb.keys_a);
+            dfree(sb.keys_b);
+            return st;
+        }
+        sb.temp = tmp;
+        sb.temp_bytes = tb;
+    }
     e = launch_harc_schedule(g->m, g->d_dag_ptr, g->d_dag_src, g->d_arc_c, D, g->d_hhist, g->d_hscan,
-                             g->d_hcur, g->d_harcs, g->d_scan_ws, s);
+                             g->d_harcs, g->d_scan_ws, sb, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    dfree(sb.keys_a);
+    dfree(sb.keys_b);
+    {
+        unsigned char* tmp = static_cast<unsigned char*>(sb.temp);
+        dfree(tmp);
+    }
     if (e != hipSuccess) return hip_fail(e, "arc schedule");
     g->h_hscan.assign((size_t)D + 1, 0);
     e = hipMemcpyAsync(g->h_hscan.data(), g->d_hscan, sizeof(int32_t) * ((size_t)D + 1), hipMemcpyDeviceToHost, s);

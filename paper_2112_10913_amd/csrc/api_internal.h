@@ -91,7 +91,6 @@ struct citron_graph {
     int32_t* d_harcs = nullptr;             // m
     int32_t* d_hhist = nullptr;             // D + 1
     int32_t* d_hscan = nullptr;             // D + 1
-    int32_t* d_hcur = nullptr;              // D
     std::vector<int32_t> h_hscan;           // heavy arcs by |C_uv|, scanned
     std::vector<int32_t> h_vscan;           // vertices by out-degree, scanned
     uint64_t tri = 0;

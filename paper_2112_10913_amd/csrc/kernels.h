@@ -30,6 +30,21 @@ hipError_t launch_peel_round(int32_t nf, const int32_t* frontier, const int32_t*
                              int32_t* deg, int32_t* round, int32_t t, int32_t r, int32_t* next, int32_t* next_cnt,
                              hipStream_t s);
 
+// ---- deterministic schedule order (kernels_sched.hip)
+struct SortBuffers {
+    unsigned long long* keys_a;   // n keys
+    unsigned long long* keys_b;   // n keys
+    void* temp;                   // sched_sort_temp_bytes(n)
+    size_t temp_bytes;
+};
+size_t sched_sort_temp_bytes(int64_t n);
+// order[0 .. *count) = vertices with out-degree >= 2 by out-degree descending, ties by id
+hipError_t sched_plan_order(int32_t n, const int32_t* dag_ptr, int32_t D, const int32_t* count, int32_t* order,
+                            const SortBuffers& sb, hipStream_t s);
+// harcs[0 .. *count) = arcs of vertices with out-degree > 64 by |C_uv| descending, ties by arc index
+hipError_t sched_heavy_arcs(int64_t m, const int32_t* dag_ptr, const int32_t* dag_src, const int32_t* arc_c,
+                            int32_t D, const int32_t* count, int32_t* harcs, const SortBuffers& sb, hipStream_t s);
+
 // ---- vertex schedule (kernels_count.hip)
 struct PlanBuffers {
     int32_t* hist;         // max_outdeg + 2
@@ -42,7 +57,7 @@ struct PlanBuffers {
 };
 hipError_t launch_plan(int32_t n, const int32_t* dag_ptr, int32_t max_outdeg, int32_t light_rows,
                        int32_t split_min_deg, int32_t split_factor, const PlanBuffers& pb,
-                       int32_t* scan_ws, hipStream_t s);
+                       int32_t* scan_ws, const SortBuffers& sb, hipStream_t s);
 hipError_t launch_fill_i32(int32_t* p, int32_t v, int64_t n, hipStream_t s);
 hipError_t launch_fill_u64(unsigned long long* p, unsigned long long v, int64_t n, hipStream_t s);
 
@@ -67,8 +82,8 @@ int32_t build_lds_bytes(int32_t light_rows, int32_t max_deg);
 hipError_t launch_rows_len(int32_t n, const int32_t* dag_ptr, int32_t* len, hipStream_t s);
 hipError_t launch_build_rows(const BuildParams& P, int32_t blocks, hipStream_t s);
 hipError_t launch_harc_schedule(int64_t m, const int32_t* dag_ptr, const int32_t* dag_src, const int32_t* arc_c,
-                                int32_t D, int32_t* hist, int32_t* hscan, int32_t* cursor, int32_t* harcs,
-                                int32_t* scan_ws, hipStream_t s);
+                                int32_t D, int32_t* hist, int32_t* hscan, int32_t* harcs,
+                                int32_t* scan_ws, const SortBuffers& sb, hipStream_t s);
 hipError_t launch_arc_c_to_u64(int64_t m, const int32_t* arc_c, unsigned long long* out, hipStream_t s);
 
 // ---- counting phase (kernels_count.hip)

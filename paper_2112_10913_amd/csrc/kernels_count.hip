@@ -1174,83 +1174,6 @@ hipError_t launch_count(const CountLaunch& cl, hipStream_t s)
     }
 }
 
-// ---------------------------------------------------------------- schedule
-
-__global__ void plan_hist_kernel(int32_t n, const int32_t* __restrict__ dag_ptr, int32_t D,
-                                 int32_t* __restrict__ hist)
-{
-    int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (u >= n) return;
-    int d = dag_ptr[u + 1] - dag_ptr[u];
-    // bucket 0 holds out-degree D, bucket D-2 holds out-degree 2 (descending)
-    if (d >= 2) atomicAdd(&hist[D - d], 1);
-}
-
-__global__ void plan_scatter_kernel(int32_t n, const int32_t* __restrict__ dag_ptr, int32_t D,
-                                    int32_t* __restrict__ cursor, int32_t* __restrict__ order)
-{
-    int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (u >= n) return;
-    int d = dag_ptr[u + 1] - dag_ptr[u];
-    if (d >= 2) order[atomicAdd(&cursor[D - d], 1)] = (int32_t)u;
-}
-
-// light_deg[j] = out-degree of order[n_heavy + j]; n_heavy and the light
-// count are read from the scanned histogram.
-__global__ void plan_light_deg_kernel(const int32_t* __restrict__ dag_ptr, const int32_t* __restrict__ order,
-                                      const int32_t* __restrict__ hist_scan, int32_t D,
-                                      int32_t* __restrict__ light_deg, int32_t n)
-{
-    int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int32_t n_heavy = D > kLightMaxDeg ? hist_scan[D - kLightMaxDeg] : 0;
-    const int32_t n_all = hist_scan[D - 1];
-    const int32_t n_light = n_all - n_heavy;
-    if (j >= n) return;
-    if (j < n_light) {
-        int u = order[n_heavy + j];
-        light_deg[j] = dag_ptr[u + 1] - dag_ptr[u];
-    } else {
-        light_deg[j] = 0;
-    }
-}
-
-__global__ void plan_batches_kernel(const int32_t* __restrict__ hist_scan, int32_t D,
-                                    const int32_t* __restrict__ light_pre, int32_t light_rows,
-                                    int32_t* __restrict__ batch_start)
-{
-    int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int32_t n_heavy = D > kLightMaxDeg ? hist_scan[D - kLightMaxDeg] : 0;
-    const int32_t n_light = hist_scan[D - 1] - n_heavy;
-    if (j >= n_light) return;
-    int b = light_pre[j] / light_rows;
-    if (j == 0 || light_pre[j - 1] / light_rows != b) batch_start[b] = (int32_t)j;
-    if (j == n_light - 1) batch_start[b + 1] = n_light;
-}
-
-__global__ void plan_header_kernel(const int32_t* __restrict__ hist_scan, int32_t D,
-                                   const int32_t* __restrict__ light_pre, int32_t light_rows,
-                                   int32_t split_min_deg, int32_t split_factor,
-                                   const int32_t* __restrict__ batch_start, PlanHeader* __restrict__ h)
-{
-    const int32_t n_heavy = D > kLightMaxDeg ? hist_scan[D - kLightMaxDeg] : 0;
-    const int32_t n_light = hist_scan[D - 1] - n_heavy;
-    int32_t n_split = 0;
-    if (split_factor > 1 && split_min_deg <= D) {
-        int32_t thr = split_min_deg > kLightMaxDeg ? split_min_deg : kLightMaxDeg + 1;
-        n_split = thr <= D ? hist_scan[D - thr + 1] : 0;
-    }
-    int32_t n_batches = n_light > 0 ? light_pre[n_light - 1] / light_rows + 1 : 0;
-    (void)batch_start;
-    h->n_heavy = n_heavy;
-    h->n_split = n_split;
-    h->split_factor = split_factor > 1 ? split_factor : 1;
-    h->n_light = n_light;
-    h->n_batches = n_batches;
-    h->n_items = n_split * h->split_factor + (n_heavy - n_split) + n_batches;
-    h->light_rows = light_rows;
-    h->max_rows = light_rows + kLightMaxDeg - 1;
-}
-
 __global__ void check_arcs_kernel(const int32_t* __restrict__ arcs, int32_t n, int64_t m, int32_t* __restrict__ err)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -1346,35 +1269,6 @@ hipError_t launch_fill_u64(u64* p, u64 v, int64_t n, hipStream_t s)
     int64_t blocks = (n + 255) / 256;
     if (blocks > 4096) blocks = 4096;
     fill_u64_kernel<<<(unsigned)blocks, 256, 0, s>>>(p, v, n);
-    return hipGetLastError();
-}
-
-hipError_t launch_plan(int32_t n, const int32_t* dag_ptr, int32_t max_outdeg, int32_t light_rows,
-                       int32_t split_min_deg, int32_t split_factor, const PlanBuffers& pb,
-                       int32_t* scan_ws, hipStream_t s)
-{
-    // D >= 2 keeps the bucket arithmetic valid for graphs without any
-    // vertex of out-degree 2 or more (the plan is then empty).
-    const int32_t D = max_outdeg > 2 ? max_outdeg : 2;
-    hipError_t e = launch_fill_i32(pb.hist, 0, D + 1, s);
-    if (e != hipSuccess) return e;
-    const unsigned nb = (unsigned)((n + 255) / 256);
-    if (n > 0) plan_hist_kernel<<<nb, 256, 0, s>>>(n, dag_ptr, D, pb.hist);
-    // hist_scan[i] = vertices with out-degree > D - i (buckets 0..i-1)
-    e = scan_exclusive(pb.hist, pb.hist_scan, D - 1, scan_ws, s);
-    if (e != hipSuccess) return e;
-    e = hipMemcpyAsync(pb.light_pre, pb.hist_scan, sizeof(int32_t) * (size_t)(D - 1),
-                       hipMemcpyDeviceToDevice, s);
-    if (e != hipSuccess) return e;
-    if (n > 0) plan_scatter_kernel<<<nb, 256, 0, s>>>(n, dag_ptr, D, pb.light_pre, pb.order);
-    if (n > 0)
-        plan_light_deg_kernel<<<nb, 256, 0, s>>>(dag_ptr, pb.order, pb.hist_scan, D, pb.light_deg, n);
-    e = scan_exclusive(pb.light_deg, pb.light_pre, n, scan_ws, s);
-    if (e != hipSuccess) return e;
-    if (n > 0)
-        plan_batches_kernel<<<nb, 256, 0, s>>>(pb.hist_scan, D, pb.light_pre, light_rows, pb.batch_start);
-    plan_header_kernel<<<1, 1, 0, s>>>(pb.hist_scan, D, pb.light_pre, light_rows, split_min_deg,
-                                       split_factor, pb.batch_start, pb.header);
     return hipGetLastError();
 }
 

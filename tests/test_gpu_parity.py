@@ -245,6 +245,20 @@ def test_count_parts_add_up(citron_gpu):
             h.count_part(5, *bad)
 
 
+def test_count_parts_across_handles(citron_gpu):
+    """Shares counted by separately loaded handles of one graph add up to the
+    count: the schedule (ties in degree and in |C_uv| included) is fixed by
+    the graph, not by the order in which threads of one build ran."""
+    graphs = ((gg.config_graph("rmat14"), (5, 7)),
+              (gg.chung_lu(n=1 << 14, w_max=2000.0, planted=40, clique_max=24, seed=7, clique_seed=8), (6,)))
+    for g, ks in graphs:
+        for k in ks:
+            want = load(citron_gpu, g).count(k)
+            nparts = 5
+            shares = [load(citron_gpu, g).count_part(k, p, nparts)[0] for p in range(nparts)]
+            assert sum(shares) % 2**64 == want, (g.name, k)
+
+
 _RMAT20 = {}
 
 
@@ -465,3 +479,32 @@ def test_device_pointer_input(citron_gpu):
     col = torch.from_numpy(g.col).cuda()
     h = citron_gpu.Graph.from_csr(rp, col).order()
     assert h.count(4) == ocount(g, 4)
+
+
+def test_outdegree_limits(citron_gpu, progress):
+    """Between the configs' largest out-degree (666) and the 4096 limit the
+    rows span up to 64 words (one per lane): closed forms on K_1500 (24-word
+    rows) up to k = 4 and K_4097 (out-degree 4096, 64-word rows) at k = 3,
+    both units; an out-degree of 4097 is refused with EINVAL."""
+    g = gg.complete(1500)
+    h = load(citron_gpu, g)
+    assert h.info()["max_outdeg"] == 1499
+    for k in (3, 4):
+        progress(f"  K_1500 k={k}")
+        assert h.count(k) == math.comb(1500, k), k
+        assert h.count_vertex_rooted(k) == math.comb(1500, k), k
+    h.free()
+    g = gg.complete(4097)
+    h = load(citron_gpu, g)
+    assert h.info()["max_outdeg"] == 4096
+    progress("  K_4097 k=3")
+    assert h.count(3) == math.comb(4097, 3)
+    h.free()
+    g = gg.complete(4098)
+    h = load(citron_gpu, g)
+    assert h.info()["max_outdeg"] == 4097
+    with pytest.raises(citron_gpu.CitronError) as e:
+        h.count(3)
+    assert e.value.status == 1
+    assert h.count(2) == g.m                 # trivial values need no rows
+    h.free()
