@@ -87,6 +87,11 @@ def load_library():
     if not os.path.exists(_LIB_PATH):
         raise ImportError(f"{_LIB_PATH} is missing: build it with "
                           "`python -m paper_2112_10913_amd.build` (hipcc, gfx950)")
+    # libcitron.so needs libamdhip64.so.7, and torch ships a copy of that
+    # runtime of its own: loading torch first binds the library to torch's
+    # copy, so that one HIP runtime serves both (torch's device pointers and
+    # streams are then valid in the library).
+    _torch()
     lib = ctypes.CDLL(_LIB_PATH)
     vp = ctypes.c_void_p
     lib.citron_load_csr.argtypes = [ctypes.c_int32, ctypes.c_int64, vp, vp, ctypes.c_uint32, vp,

@@ -117,7 +117,6 @@ static void dfree(T*& p)
 
 static void free_plan(citron_graph* g)
 {
-    dfree(g->pb.hist);
     dfree(g->pb.hist_scan);
     dfree(g->pb.order);
     dfree(g->pb.light_deg);
@@ -145,7 +144,6 @@ static void free_graph_memory(citron_graph* g)
     dfree(g->d_rows);
     dfree(g->d_arc_c);
     dfree(g->d_harcs);
-    dfree(g->d_hhist);
     dfree(g->d_hscan);
     for (int32_t* p : g->retired_buckets) dfree(p);
     g->retired_buckets.clear();
@@ -174,8 +172,7 @@ citron_status ensure_plan(citron_graph* g, const citron_tuning& t)
         // what it allocated and a retry allocates only the rest
         int64_t* acct = &g->device_bytes;
         citron_status st;
-        if ((!g->pb.hist && (st = dalloc(&g->pb.hist, (size_t)D + 2, acct, "plan"))) ||
-            (!g->pb.hist_scan && (st = dalloc(&g->pb.hist_scan, (size_t)D + 3, acct, "plan"))) ||
+        if ((!g->pb.hist_scan && (st = dalloc(&g->pb.hist_scan, (size_t)D + 3, acct, "plan"))) ||
             (!g->pb.order && (st = dalloc(&g->pb.order, (size_t)g->n + 1, acct, "plan"))) ||
             (!g->pb.light_deg && (st = dalloc(&g->pb.light_deg, (size_t)g->n + 1, acct, "plan"))) ||
             (!g->pb.light_pre && (st = dalloc(&g->pb.light_pre, (size_t)g->n + 2, acct, "plan"))) ||
@@ -238,7 +235,6 @@ citron_status ensure_rows(citron_graph* g)
     if ((!g->d_rows_off && (st = dalloc(&g->d_rows_off, (size_t)g->n + 1, acct, "row offsets"))) ||
         (!g->d_arc_c && (st = dalloc(&g->d_arc_c, (size_t)g->m, acct, "arc sizes"))) ||
         (!g->d_harcs && (st = dalloc(&g->d_harcs, (size_t)g->m, acct, "heavy arcs"))) ||
-        (!g->d_hhist && (st = dalloc(&g->d_hhist, (size_t)D + 1, acct, "arc histogram"))) ||
         (!g->d_hscan && (st = dalloc(&g->d_hscan, (size_t)D + 1, acct, "arc histogram"))))
         return st;
     // Row offsets are int32, so the rows of all vertices, sum over u of
@@ -310,8 +306,7 @@ citron_status ensure_rows(citron_graph* g)
         sb.temp = tmp;
         sb.temp_bytes = tb;
     }
-    e = launch_harc_schedule(g->m, g->d_dag_ptr, g->d_dag_src, g->d_arc_c, D, g->d_hhist, g->d_hscan,
-                             g->d_harcs, g->d_scan_ws, sb, s);
+    e = sched_heavy_arcs(g->m, g->d_dag_ptr, g->d_dag_src, g->d_arc_c, D, g->d_hscan, g->d_harcs, sb, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     dfree(sb.keys_a);
     dfree(sb.keys_b);

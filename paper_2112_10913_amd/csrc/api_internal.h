@@ -89,7 +89,6 @@ struct citron_graph {
     unsigned long long* d_rows = nullptr;
     int32_t* d_arc_c = nullptr;             // m
     int32_t* d_harcs = nullptr;             // m
-    int32_t* d_hhist = nullptr;             // D + 1
     int32_t* d_hscan = nullptr;             // D + 1
     std::vector<int32_t> h_hscan;           // heavy arcs by |C_uv|, scanned
     std::vector<int32_t> h_vscan;           // vertices by out-degree, scanned

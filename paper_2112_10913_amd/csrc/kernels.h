@@ -38,16 +38,17 @@ struct SortBuffers {
     size_t temp_bytes;
 };
 size_t sched_sort_temp_bytes(int64_t n);
-// order[0 .. *count) = vertices with out-degree >= 2 by out-degree descending, ties by id
-hipError_t sched_plan_order(int32_t n, const int32_t* dag_ptr, int32_t D, const int32_t* count, int32_t* order,
+// order[0 .. bounds[D-1]) = vertices with out-degree >= 2 by out-degree
+// descending, ties by id; bounds[i] (i < D) = vertices of out-degree > D - i
+hipError_t sched_plan_order(int32_t n, const int32_t* dag_ptr, int32_t D, int32_t* bounds, int32_t* order,
                             const SortBuffers& sb, hipStream_t s);
-// harcs[0 .. *count) = arcs of vertices with out-degree > 64 by |C_uv| descending, ties by arc index
+// harcs[0 .. bounds[D]) = arcs of vertices with out-degree > 64 by |C_uv|
+// descending, ties by arc index; bounds[i] (i <= D) = those with |C_uv| > D - 1 - i
 hipError_t sched_heavy_arcs(int64_t m, const int32_t* dag_ptr, const int32_t* dag_src, const int32_t* arc_c,
-                            int32_t D, const int32_t* count, int32_t* harcs, const SortBuffers& sb, hipStream_t s);
+                            int32_t D, int32_t* bounds, int32_t* harcs, const SortBuffers& sb, hipStream_t s);
 
-// ---- vertex schedule (kernels_count.hip)
+// ---- vertex schedule (kernels_sched.hip)
 struct PlanBuffers {
-    int32_t* hist;         // max_outdeg + 2
     int32_t* hist_scan;    // max_outdeg + 3
     int32_t* order;        // n
     int32_t* light_deg;    // n
@@ -81,9 +82,6 @@ struct BuildParams {
 int32_t build_lds_bytes(int32_t light_rows, int32_t max_deg);
 hipError_t launch_rows_len(int32_t n, const int32_t* dag_ptr, int32_t* len, hipStream_t s);
 hipError_t launch_build_rows(const BuildParams& P, int32_t blocks, hipStream_t s);
-hipError_t launch_harc_schedule(int64_t m, const int32_t* dag_ptr, const int32_t* dag_src, const int32_t* arc_c,
-                                int32_t D, int32_t* hist, int32_t* hscan, int32_t* harcs,
-                                int32_t* scan_ws, const SortBuffers& sb, hipStream_t s);
 hipError_t launch_arc_c_to_u64(int64_t m, const int32_t* arc_c, unsigned long long* out, hipStream_t s);
 
 // ---- counting phase (kernels_count.hip)

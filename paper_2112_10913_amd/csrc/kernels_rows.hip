@@ -253,18 +253,6 @@ __global__ void rows_len_kernel(int32_t n, const int32_t* __restrict__ dag_ptr, 
     len[u] = d * ((d + 63) >> 6);
 }
 
-// Heavy arcs (source out-degree > 64) by |C_uv|, descending: bucket D-1-c
-// (the histogram; the order itself comes from kernels_sched.hip).
-__global__ void harc_hist_kernel(int64_t m, const int32_t* __restrict__ dag_ptr,
-                                 const int32_t* __restrict__ dag_src, const int32_t* __restrict__ arc_c,
-                                 int32_t D, int32_t* __restrict__ hist)
-{
-    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= m) return;
-    const int u = dag_src[e];
-    if (dag_ptr[u + 1] - dag_ptr[u] > kLightMaxDeg) atomicAdd(&hist[D - 1 - arc_c[e]], 1);
-}
-
 // per_arc[e] = |C_uv| (the k = 3 per-arc counts)
 __global__ void arc_c_to_u64_kernel(int64_t m, const int32_t* __restrict__ arc_c, u64* __restrict__ out)
 {
@@ -290,20 +278,6 @@ hipError_t launch_build_rows(const BuildParams& P, int32_t blocks, hipStream_t s
     }
     build_rows_kernel<<<blocks, 256, lds, s>>>(P);
     return hipGetLastError();
-}
-
-hipError_t launch_harc_schedule(int64_t m, const int32_t* dag_ptr, const int32_t* dag_src, const int32_t* arc_c,
-                                int32_t D, int32_t* hist, int32_t* hscan, int32_t* harcs,
-                                int32_t* scan_ws, const SortBuffers& sb, hipStream_t s)
-{
-    hipError_t e = launch_fill_i32(hist, 0, D + 1, s);
-    if (e != hipSuccess || m <= 0) return e;
-    const unsigned blocks = (unsigned)((m + 255) / 256);
-    harc_hist_kernel<<<blocks, 256, 0, s>>>(m, dag_ptr, dag_src, arc_c, D, hist);
-    e = scan_exclusive(hist, hscan, D, scan_ws, s);
-    if (e != hipSuccess) return e;
-    // the hscan[D] heavy arcs by |C_uv| descending, ties by arc index
-    return sched_heavy_arcs(m, dag_ptr, dag_src, arc_c, D, hscan + D, harcs, sb, s);
 }
 
 hipError_t launch_arc_c_to_u64(int64_t m, const int32_t* arc_c, u64* out, hipStream_t s)

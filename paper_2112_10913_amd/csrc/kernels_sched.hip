@@ -10,7 +10,8 @@
 // every process, and shares counted by different handles of one graph add
 // up to the count.  Each order is a device radix sort of 64-bit keys
 // (bucket << 32 | id); entries outside the schedule get the largest key and
-// sort to the end.
+// sort to the end.  The bucket sizes (the scans the schedule indexes by
+// bucket) are read off the sorted keys, with no histogram atomics.
 #include "kernels.h"
 
 #include <hipcub/device/device_radix_sort.hpp>
@@ -40,6 +41,25 @@ __global__ void harc_keys_kernel(int64_t m, const int32_t* __restrict__ dag_ptr,
     keys[e] = heavy ? ((u64)(unsigned)(D - 1 - arc_c[e]) << 32) | (u64)e : ~0ull;
 }
 
+// bounds[b] = number of sorted keys with bucket < b, for b = 0..nb, where
+// the bucket of a key is its high word (the sentinel ~0 counts as bucket
+// nb): thread i fills the bounds between the buckets of keys i - 1 and i.
+__global__ void bucket_bounds_kernel(int64_t n, const u64* __restrict__ keys, int32_t nb, int32_t* __restrict__ bounds)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const unsigned hi = (unsigned)(keys[i] >> 32);
+    const int b = hi < (unsigned)nb ? (int)hi : nb;
+    int prev = -1;
+    if (i > 0) {
+        const unsigned ph = (unsigned)(keys[i - 1] >> 32);
+        prev = ph < (unsigned)nb ? (int)ph : nb;
+    }
+    for (int x = prev + 1; x <= b; ++x) bounds[x] = (int32_t)i;
+    if (i == n - 1)
+        for (int x = b + 1; x <= nb; ++x) bounds[x] = (int32_t)n;
+}
+
 // out[i] = low word of keys[i] for i < *count (the entries in the schedule)
 __global__ void unpack_keys_kernel(int64_t n, const u64* __restrict__ keys, const int32_t* __restrict__ count,
                                    int32_t* __restrict__ out)
@@ -58,47 +78,42 @@ size_t sched_sort_temp_bytes(int64_t n)
     return bytes > 0 ? bytes : 1;
 }
 
-hipError_t sched_plan_order(int32_t n, const int32_t* dag_ptr, int32_t D, const int32_t* count, int32_t* order,
+// Sorted keys -> bounds of nb buckets -> the ids of the first bounds[nb].
+static hipError_t sort_and_split(int64_t n, int32_t nb, int32_t* bounds, int32_t* out, const SortBuffers& sb,
+                                 hipStream_t s)
+{
+    const unsigned blocks = (unsigned)((n + 255) / 256);
+    size_t tb = sb.temp_bytes;
+    hipError_t e = hipcub::DeviceRadixSort::SortKeys(sb.temp, tb, (const u64*)sb.keys_a, sb.keys_b, (int)n, 0, 64, s);
+    if (e != hipSuccess) return e;
+    bucket_bounds_kernel<<<blocks, 256, 0, s>>>(n, sb.keys_b, nb, bounds);
+    unpack_keys_kernel<<<blocks, 256, 0, s>>>(n, sb.keys_b, bounds + nb, out);
+    return hipGetLastError();
+}
+
+hipError_t sched_plan_order(int32_t n, const int32_t* dag_ptr, int32_t D, int32_t* bounds, int32_t* order,
                             const SortBuffers& sb, hipStream_t s)
 {
-    if (n <= 0) return hipSuccess;
-    const unsigned blocks = (unsigned)((n + 255) / 256);
-    plan_keys_kernel<<<blocks, 256, 0, s>>>(n, dag_ptr, D, sb.keys_a);
+    if (n <= 0) return launch_fill_i32(bounds, 0, D, s);
+    plan_keys_kernel<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(n, dag_ptr, D, sb.keys_a);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    size_t tb = sb.temp_bytes;
-    e = hipcub::DeviceRadixSort::SortKeys(sb.temp, tb, (const u64*)sb.keys_a, sb.keys_b, (int)n, 0, 64, s);
-    if (e != hipSuccess) return e;
-    unpack_keys_kernel<<<blocks, 256, 0, s>>>(n, sb.keys_b, count, order);
-    return hipGetLastError();
+    // buckets D - d for d = D .. 2: D - 1 of them
+    return sort_and_split(n, D - 1, bounds, order, sb, s);
 }
 
 hipError_t sched_heavy_arcs(int64_t m, const int32_t* dag_ptr, const int32_t* dag_src, const int32_t* arc_c,
-                            int32_t D, const int32_t* count, int32_t* harcs, const SortBuffers& sb, hipStream_t s)
+                            int32_t D, int32_t* bounds, int32_t* harcs, const SortBuffers& sb, hipStream_t s)
 {
-    if (m <= 0) return hipSuccess;
-    const unsigned blocks = (unsigned)((m + 255) / 256);
-    harc_keys_kernel<<<blocks, 256, 0, s>>>(m, dag_ptr, dag_src, arc_c, D, sb.keys_a);
+    if (m <= 0) return launch_fill_i32(bounds, 0, D + 1, s);
+    harc_keys_kernel<<<(unsigned)((m + 255) / 256), 256, 0, s>>>(m, dag_ptr, dag_src, arc_c, D, sb.keys_a);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    size_t tb = sb.temp_bytes;
-    e = hipcub::DeviceRadixSort::SortKeys(sb.temp, tb, (const u64*)sb.keys_a, sb.keys_b, (int)m, 0, 64, s);
-    if (e != hipSuccess) return e;
-    unpack_keys_kernel<<<blocks, 256, 0, s>>>(m, sb.keys_b, count, harcs);
-    return hipGetLastError();
+    // buckets D - 1 - c for c = D - 1 .. 0: D of them
+    return sort_and_split(m, D, bounds, harcs, sb, s);
 }
 
 // ---------------------------------------------------------------- plan
-
-__global__ void plan_hist_kernel(int32_t n, const int32_t* __restrict__ dag_ptr, int32_t D,
-                                 int32_t* __restrict__ hist)
-{
-    int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (u >= n) return;
-    int d = dag_ptr[u + 1] - dag_ptr[u];
-    // bucket 0 holds out-degree D, bucket D-2 holds out-degree 2 (descending)
-    if (d >= 2) atomicAdd(&hist[D - d], 1);
-}
 
 // light_deg[j] = out-degree of order[n_heavy + j]; n_heavy and the light
 // count are read from the scanned histogram.
@@ -163,16 +178,11 @@ hipError_t launch_plan(int32_t n, const int32_t* dag_ptr, int32_t max_outdeg, in
     // D >= 2 keeps the bucket arithmetic valid for graphs without any
     // vertex of out-degree 2 or more (the plan is then empty).
     const int32_t D = max_outdeg > 2 ? max_outdeg : 2;
-    hipError_t e = launch_fill_i32(pb.hist, 0, D + 1, s);
-    if (e != hipSuccess) return e;
     const unsigned nb = (unsigned)((n + 255) / 256);
-    if (n > 0) plan_hist_kernel<<<nb, 256, 0, s>>>(n, dag_ptr, D, pb.hist);
-    // hist_scan[i] = vertices with out-degree > D - i (buckets 0..i-1)
-    e = scan_exclusive(pb.hist, pb.hist_scan, D - 1, scan_ws, s);
-    if (e != hipSuccess) return e;
-    // vertices of out-degree >= 2 (hist_scan[D - 1] of them) by out-degree
-    // descending, ties by id: the same order in every process
-    e = sched_plan_order(n, dag_ptr, D, pb.hist_scan + (D - 1), pb.order, sb, s);
+    // order: vertices of out-degree >= 2 by out-degree descending, ties by
+    // id (the same order in every process); hist_scan[i] = vertices with
+    // out-degree > D - i (buckets 0..i-1), hist_scan[D - 1] = all of them
+    hipError_t e = sched_plan_order(n, dag_ptr, D, pb.hist_scan, pb.order, sb, s);
     if (e != hipSuccess) return e;
     if (n > 0)
         plan_light_deg_kernel<<<nb, 256, 0, s>>>(dag_ptr, pb.order, pb.hist_scan, D, pb.light_deg, n);
