@@ -118,7 +118,6 @@ hipError_t launch_gather_arc_c(const int32_t* arcs, int32_t n, const int32_t* ar
 
 // ---- k-clique listing (kernels_list.hip)
 constexpr int kListMaxK = 16;                    // largest k listing supports
-constexpr int kListMaxLevels = kListMaxK - 2;    // open search levels per wave
 struct ListParams {
     const int32_t* arcs;         // listed arcs (DAG arc indices)
     int32_t n_arcs;

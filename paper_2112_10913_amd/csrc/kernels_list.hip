@@ -9,7 +9,8 @@
 // One wave per arc at a time (a persistent grid pulls arcs from one
 // cursor).  The search state is wave-uniform, lane q holding word q of each
 // candidate mask over the positions of N->(u), as in the heavy count engine;
-// the masks of the open levels live in the wave's LDS.  At the last level
+// the masks of the open levels live in the wave's LDS, k - 2 levels of one
+// word per lane (3 KB per wave at k = 5, 14 KB at k = 16).  At the last level
 // every candidate completes a clique: lane j writes the clique of the j-th
 // set bit, so the output rows of one node are written in one step.  The
 // offsets of the arcs' output come from their exact counts (a scan of the
@@ -55,16 +56,25 @@ __device__ __forceinline__ int select64(u64 v, int r)
     return pos;
 }
 
+// Levels whose masks are kept for the way back: a node at level t is
+// pushed only while k - 2 - t >= 2 vertices remain to choose, so levels
+// 0 .. k - 4 are stored; k - 2 (at least 1) bounds them.
+__host__ __device__ __forceinline__ int list_levels(int k) { return k > 3 ? k - 2 : 1; }
+
 }  // namespace
 
 __global__ void __launch_bounds__(kListBlock) list_arcs_kernel(ListParams P)
 {
-    __shared__ u64 sM[kListWaves][kListMaxLevels][kWave];
-    __shared__ u64 sR[kListWaves][kListMaxLevels][kWave];
+    // the open levels' masks, k - 2 levels per wave (sized at launch, so
+    // that small k leaves LDS for more resident waves)
+    extern __shared__ u64 lds_levels[];
     __shared__ int32_t sPre[kListWaves][kListMaxK];
     const int lane = lane_of();
     const int wid = threadIdx.x / kWave;
     const int k = P.k;
+    const int levels = list_levels(k);
+    u64* const sM = lds_levels + (size_t)wid * levels * kWave;
+    u64* const sR = lds_levels + (size_t)(kListWaves + wid) * levels * kWave;
     for (;;) {
         int i = 0;
         if (lane == 0) i = atomicAdd(P.cursor, 1);
@@ -133,8 +143,8 @@ __global__ void __launch_bounds__(kListBlock) list_arcs_kernel(ListParams P)
                 if (b == 0ull) {
                     if (t == 0) break;
                     --t;
-                    M = sM[wid][t][lane];
-                    R = sR[wid][t][lane];
+                    M = sM[t * kWave + lane];
+                    R = sR[t * kWave + lane];
                     continue;
                 }
                 const int f = __builtin_ctzll(b);
@@ -147,8 +157,8 @@ __global__ void __launch_bounds__(kListBlock) list_arcs_kernel(ListParams P)
                 for (int o = kWave / 2; o > 0; o >>= 1) cc += __shfl_xor(cc, o, kWave);
                 if (cc >= need - 1) {
                     // descend: the level's state is kept for the way back
-                    sM[wid][t][lane] = M;
-                    sR[wid][t][lane] = R;
+                    sM[t * kWave + lane] = M;
+                    sR[t * kWave + lane] = R;
                     if (lane == 0) sPre[wid][2 + t] = P.dag_col[a0 + x];
                     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
                     __builtin_amdgcn_wave_barrier();
@@ -167,7 +177,8 @@ hipError_t launch_list_arcs(const ListParams& P, int32_t blocks, hipStream_t s)
 {
     if (P.n_arcs <= 0) return hipSuccess;
     if (P.k < 2 || P.k > kListMaxK) return hipErrorInvalidValue;
-    list_arcs_kernel<<<blocks, kListBlock, 0, s>>>(P);
+    const size_t lds = 2 * (size_t)kListWaves * list_levels(P.k) * kWave * sizeof(u64);
+    list_arcs_kernel<<<blocks, kListBlock, lds, s>>>(P);
     return hipGetLastError();
 }
 
