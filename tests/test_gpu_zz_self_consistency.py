@@ -4,8 +4,10 @@ Their per-arc values are checked against the oracle on sampled arcs
 elsewhere; here the whole count must not change when the vertex ids are
 randomly permuted (another DAG, other subgraphs, another work schedule) or
 when the launch is tuned differently (other split factors, LDS copy limit
-and launch shape).  This pins those cells by self-consistency only, not by
-an independent value.
+and launch shape), when the graph is oriented by the core ordering instead
+(Algorithm 1: another DAG with another largest out-degree, hence other
+subgraphs), or when the paper's vertex-rooted unit counts it.  This pins
+those cells by self-consistency only, not by an independent value.
 """
 import sys
 
@@ -22,13 +24,24 @@ def say(*a):
     sys.stdout.flush()
 
 
-def _counts_agree(citron, name, k):
+def _counts_agree(citron, name, k, vertex_unit=False):
     g = gg.config_graph(name)
     say(f"{name}: generated n={g.n} m={g.m}")
     h = citron.Graph.from_csr(g.row_ptr, g.col).order()
     base = h.count(k)
+    deg_max = h.info()["max_outdeg"]
     say(f"{name} k={k}: {base}")
+    if vertex_unit:
+        got = h.count_vertex_rooted(k)
+        say(f"{name} vertex-rooted k={k}: {got}")
+        assert got == base, (name, k, "vertex unit")
     h.free()
+    h = citron.Graph.from_csr(g.row_ptr, g.col).order("core")
+    got = h.count(k)
+    say(f"{name} core ordering (largest out-degree {h.info()['max_outdeg']} vs {deg_max}) k={k}: {got}")
+    assert h.info()["max_outdeg"] < deg_max
+    h.free()
+    assert got == base, (name, k, "core ordering")
     for seed, tuning in ((1, None),
                          (2, citron.Tuning(wg_waves=2, blocks_per_cu=4, split_pct=50, arc_lds_max=192))):
         r = gg.relabel(g, np.random.default_rng(seed).permutation(g.n))
@@ -43,7 +56,7 @@ def _counts_agree(citron, name, k):
 
 
 def test_rmat20_k6_relabel_and_tuning_invariant(citron_gpu):
-    _counts_agree(citron_gpu, "rmat20", 6)
+    _counts_agree(citron_gpu, "rmat20", 6, vertex_unit=True)
 
 
 def test_chunglu22_k6_relabel_and_tuning_invariant(citron_gpu):
