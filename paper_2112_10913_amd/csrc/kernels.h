@@ -130,6 +130,8 @@ struct ListParams {
     const long long* offsets;    // n_arcs + 1: first output clique of each arc
     int32_t* out;                // cliques, k ids each
     int32_t* cursor;             // zeroed before the launch
+    int32_t chunk;               // arcs a wave claims per atomic (set by launch_list_arcs)
+    int32_t stride;              // claim j lists arc j * stride mod n_arcs (set by launch_list_arcs)
     int32_t* err;                // zeroed before the launch; 1 = slot overrun, 2 = count mismatch
 };
 hipError_t launch_list_arcs(const ListParams& P, int32_t blocks, hipStream_t s);

@@ -44,6 +44,7 @@ constexpr int kDonateMinIdle = 8;       // idle lanes that trigger work donation
 constexpr int kBurstIters = 32;         // last-level steps of one leaf burst at most
 constexpr int kBurstMinLanes = 32;      // lanes at a last-level node to keep a burst going
 constexpr int kN3Burst = 8;             // two-level steps between refills of idle lanes
+constexpr int kMaxClaim = 16;           // items a wave claims at once, at most
 // donation mailbox per lane: M, R, (need, base), and the arc tag of per-arc launches
 __host__ __device__ constexpr int mbox_words(bool per_arc) { return per_arc ? 4 : 3; }
 constexpr int kPosList = 3 * kWave * 2; // candidate positions the smaller mailbox area holds (1.5 KB)
@@ -920,6 +921,7 @@ struct KParams {
     int32_t flush_rows;     // a wave runs its queue once it holds this many rows
     int32_t arc_lds_max;    // representation switch of heavy nodes (64..kArcMaxC)
     int32_t* progress;      // host-mapped word: items claimed, updated every 512 (nullable)
+    int32_t chunk;          // consecutive items a wave claims with one atomic
 };
 
 template <int kMode, bool kStats, bool kPerArc>
@@ -982,10 +984,16 @@ __global__ void __launch_bounds__(kMaxBlock) __attribute__((amdgpu_waves_per_eu(
     }
     u64 item_max = 0ull;
 
+    int g_next = 0, g_end = 0;         // the wave's claimed run of items
     for (;;) {
-        int g = 0;
-        if (lane == 0) g = atomicAdd(P.item_ctr, 1);
-        g = __shfl(g, 0, kWave);
+        if (g_next >= g_end) {
+            int g0 = 0;
+            if (lane == 0) g0 = atomicAdd(P.item_ctr, P.chunk);
+            g0 = __shfl(g0, 0, kWave);
+            g_next = g0;
+            g_end = g0 + P.chunk;
+        }
+        const int g = g_next++;
         if (g >= P.total_items) break;
         // progress for the host, read without any HIP call while the launch runs
         if (P.progress && lane == 0 && (g & 511) == 0)
@@ -1167,6 +1175,20 @@ hipError_t launch_count(const CountLaunch& cl, hipStream_t s)
     P.flush_rows = cl.flush_rows > kWaveBufRows ? kWaveBufRows : cl.flush_rows;
     P.arc_lds_max = clamp_arc_max(cl.arc_lds_max);
     P.progress = cl.progress;
+    // Items claimed per atomic.  All waves claim from one device-wide
+    // counter, whose atomics are serialised (about 12 ns each on MI355X, so
+    // one item per claim caps a launch near 85 M items/s); a wave claims a
+    // run of consecutive items instead, short enough that every wave still
+    // makes about eight claims.  Items are in descending cost order, so the
+    // items of a run cost about the same.
+    {
+        const int64_t waves = (int64_t)cl.blocks * cl.wg_waves;
+        int64_t c = (int64_t)cl.total_items / (waves * 8);
+        c = c < 1 ? 1 : (c > kMaxClaim ? kMaxClaim : c);
+        // the counter ends at most waves * chunk past total_items
+        if ((int64_t)cl.total_items + waves * c >= (1ll << 31)) c = 1;
+        P.chunk = (int32_t)c;
+    }
     switch (stack_mode(cl.max_k)) {
     case kStackReg: return launch_mode<kStackReg>(P, cl, s);
     case kStackLds: return launch_mode<kStackLds>(P, cl, s);

@@ -19,6 +19,8 @@
 // flag instead of writing outside it.
 #include "kernels.h"
 
+#include <numeric>
+
 namespace citron {
 
 namespace {
@@ -75,11 +77,21 @@ __global__ void __launch_bounds__(kListBlock) list_arcs_kernel(ListParams P)
     const int levels = list_levels(k);
     u64* const sM = lds_levels + (size_t)wid * levels * kWave;
     u64* const sR = lds_levels + (size_t)(kListWaves + wid) * levels * kWave;
+    int i_next = 0, i_end = 0;          // the wave's claimed run of arcs
     for (;;) {
-        int i = 0;
-        if (lane == 0) i = atomicAdd(P.cursor, 1);
-        i = __shfl(i, 0, kWave);
-        if (i >= P.n_arcs) break;
+        if (i_next >= i_end) {
+            int i0 = 0;
+            if (lane == 0) i0 = atomicAdd(P.cursor, P.chunk);
+            i0 = __shfl(i0, 0, kWave);
+            i_next = i0;
+            i_end = i0 + P.chunk;
+        }
+        const int j = i_next++;
+        if (j >= P.n_arcs) break;
+        // claim j lists arc j * stride mod n_arcs (stride coprime to
+        // n_arcs): a run of claims spreads over the list, so the arcs of one
+        // heavy vertex, adjacent in DAG order, do not land in one wave's run
+        const int i = (int)(((long long)j * P.stride) % P.n_arcs);
         const int e = P.arcs[i];
         const int u = P.dag_src[e];
         const int a0 = P.dag_ptr[u];
@@ -178,7 +190,26 @@ hipError_t launch_list_arcs(const ListParams& P, int32_t blocks, hipStream_t s)
     if (P.n_arcs <= 0) return hipSuccess;
     if (P.k < 2 || P.k > kListMaxK) return hipErrorInvalidValue;
     const size_t lds = 2 * (size_t)kListWaves * list_levels(P.k) * kWave * sizeof(u64);
-    list_arcs_kernel<<<blocks, kListBlock, lds, s>>>(P);
+    // arcs claimed per atomic on the shared cursor (its atomics are
+    // serialised): runs of up to 16 arcs, about eight claims per wave
+    ListParams Q = P;
+    const int64_t waves = (int64_t)blocks * kListWaves;
+    int64_t c = (int64_t)P.n_arcs / (waves * 8);
+    c = c < 1 ? 1 : (c > 16 ? 16 : c);
+    if ((int64_t)P.n_arcs + waves * c >= (1ll << 31)) c = 1;
+    Q.chunk = (int32_t)c;
+    // a stride near 0.618 n_arcs (consecutive claims then land far apart,
+    // as in Fibonacci hashing) that shares no factor with n_arcs
+    int64_t st = 1;
+    if (c > 1) {
+        for (int64_t t = (int64_t)(0.6180339887 * P.n_arcs); t < P.n_arcs; ++t)
+            if (std::gcd(t, (int64_t)P.n_arcs) == 1) {
+                st = t;
+                break;
+            }
+    }
+    Q.stride = (int32_t)st;
+    list_arcs_kernel<<<blocks, kListBlock, lds, s>>>(Q);
     return hipGetLastError();
 }
 
