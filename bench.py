@@ -30,7 +30,7 @@ The CPU baseline is the oracle on the host's cores (one process per core, at
 most 16, roots dealt by residue class) on a sample of the roots, for the
 smallest k of the step, run before the GPU is touched.
 
-Prints ONE JSON line.  Only N=1 is supported: this build targets one GPU.
+Prints ONE JSON line.  Only N=1 is supported: the library runs on one GPU.
 """
 from __future__ import annotations
 
@@ -508,7 +508,7 @@ def main():
         return
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+        print("bench.py runs on one GPU only: the library has no multi-GPU path "
               "(--gpus 1)", file=sys.stderr)
         sys.exit(2)
 
